@@ -1,0 +1,58 @@
+"""ctypes loader of the plain-C FP64 CPU baseline (cpu_baseline.c).  Test
+infrastructure only; built by ``build()`` (gcc -O2 -fopenmp)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cpu_baseline.c")
+LIB = os.path.join(HERE, "_cpu_baseline.so")
+
+
+def build() -> str:
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", SRC, "-o", LIB + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError("oracle CPU baseline not built: run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        lib.oracle_cheb_filter.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, P, ctypes.c_int,
+                                           P, ctypes.c_int64, P]
+        lib.oracle_cheb_filter.restype = ctypes.c_int
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def cheb_filter(n, row_ptr, col_idx, w, lmax, a, R):
+    """Y = sum_j a_j T_j(L~) R in float64 (w None for unit weights)."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w64 = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    Y = np.empty_like(R)
+    rc = lib.oracle_cheb_filter(n, rp.ctypes.data, ci.ctypes.data, None if w64 is None else w64.ctypes.data,
+                                float(lmax), a.ctypes.data, len(a) - 1, R.ctypes.data, R.shape[1], Y.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle CPU baseline allocation failed")
+    return Y
