@@ -1,0 +1,218 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic batch:
+strengths -> lambda_max (Lanczos) -> lambda_k (Chebyshev moments + eigenvalue-
+count dichotomy) -> coefficients -> polynomial filter of the R random signals
+-> row normalisation -> k-means (init rows, iterations of assign + update,
+final assign).
+
+Default workload: stochastic block model, N = 1,000,000 nodes, 50 communities
+with Dirichlet(5) sizes, mean degree 30, p_out/p_in = 0.05, unit weights
+stored as float32; R = 96 signals, order p = 150, 12 dichotomy steps, k = 50,
+10 k-means iterations.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is the filter's algorithmic HBM throughput
+(GB/s): p x B_step / (measured filter time), with
+B_step = 4(N+1) + 8 nnz + 4N + 3 N R b_T + 2 N R 4 (row offsets, column
+indices and weights, diagonal, T_j / T_{j-1} / T_{j+1}, read+write of Y).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def b_step(n, nnz, r, bt, weighted=True):
+    return 4 * (n + 1) + nnz * (4 + (4 if weighted else 0)) + 4 * n + 3 * n * r * bt + 2 * n * r * 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3, choices=[2, 3])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=8)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_1509_08863_amd as asc
+
+    dev = "cuda:0"
+    cfg = W.CONFIGS[args.config]
+    seeds = W.config_seeds(args.config)
+    t0 = time.time()
+    g = W.config_graph(args.config)
+    n, nnz, r, p, k = g.n, g.nnz, cfg["r"], cfg["p"], cfg["k"]
+    steps_dich, km_iters = cfg["steps"], cfg["kmeans_iters"]
+    R32, R64 = W.signals(n, r, seeds["signals"])
+    Rbf, Rbf64 = W.signals(n, r, seeds["signals"], "bf16")
+    v0 = W.start_vector(n, seeds["lanczos"])
+    init = W.init_rows(n, k, seeds["kmeans"])
+    gen_s = time.time() - t0
+
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    w = torch.from_numpy(g.weights_or_ones()).to(dev)
+    G = asc.graph_prepare(rp, ci, w)
+    R = torch.from_numpy(R32).to(dev)
+    Rb = torch.from_numpy(Rbf.view(np.int16)).to(dev).view(torch.bfloat16)
+    v0d = torch.from_numpy(v0).to(dev)
+    initd = torch.from_numpy(init).to(dev)
+    Y = torch.empty(n, r, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    comp_names = ["prepare", "lmax", "lambda_k", "coeffs", "filter", "normalize", "kmeans"]
+
+    def step(rec=None):
+        marks = [ev() for _ in range(len(comp_names) + 1)]
+        marks[0].record()
+        Gs = asc.graph_prepare(rp, ci, w)
+        marks[1].record()
+        lmax = asc.lmax_estimate(Gs, v0d, 60)
+        marks[2].record()
+        lam_k, _ = asc.eigcount_lambda_k(Gs, lmax, k, p, steps_dich, R)
+        marks[3].record()
+        a = asc.cheb_coeffs(lam_k, lmax, p)
+        marks[4].record()
+        asc.cheb_filter(Gs, lmax, a, R, Y)
+        marks[5].record()
+        asc.normalize_features(Y, want_norms=False)
+        marks[6].record()
+        C = asc.kmeans_init_rows(Y, initd)
+        for _ in range(km_iters):
+            lab, _ = asc.kmeans_assign(Y, C)
+            asc.kmeans_update(Y, lab, C)
+        lab, _ = asc.kmeans_assign(Y, C)
+        marks[7].record()
+        if rec is not None:
+            rec.append(marks)
+        return lmax, lam_k, lab
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        out = step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    comp = {nm: 0.0 for nm in comp_names}
+    for marks in recs:
+        for q, nm in enumerate(comp_names):
+            comp[nm] += marks[q].elapsed_time(marks[q + 1]) / len(recs)
+    ms_step = wall * 1e3 / args.steps
+    lmax_h = float(out[0].cpu()[0])
+    lam_k_h = float(out[1].cpu()[0])
+
+    # filter alone (fp32 and bf16), events on the launch stream
+    def time_filter(Rin, reps=5):
+        a = asc.cheb_coeffs(out[1], out[0], p)
+        asc.cheb_filter(G, out[0], a, Rin, Y)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            asc.cheb_filter(G, out[0], a, Rin, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_f32 = time_filter(R)
+    ms_bf16 = None if args.no_bf16 else time_filter(Rb)
+    bs32 = b_step(n, nnz, r, 4)
+    bs16 = b_step(n, nnz, r, 2)
+    gbs32 = p * bs32 / (ms_f32 * 1e-3) / 1e9
+    gbs16 = None if ms_bf16 is None else p * bs16 / (ms_bf16 * 1e-3) / 1e9
+
+    # error against FP64 on a column sample, same launch configuration
+    err = {}
+    cpu = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle
+        import oracle.cpu_baseline as cb
+        if not os.path.exists(cb.LIB):
+            cb.build()
+        L = oracle.laplacian_sparse(n, g.row_ptr, g.col_idx, None)
+        s = oracle.strength(n, g.row_ptr, g.col_idx, None)
+        lmax_o = oracle.lmax_estimate(L, s, v0, 40)
+        lc_o = 0.17 * lmax_o
+        a_o = oracle.cheb_coeffs(lc_o, lmax_o, p)
+        cols = args.cpu_cols
+        t1 = time.perf_counter()
+        Yref = cb.cheb_filter(n, g.row_ptr, g.col_idx, None, lmax_o, a_o, R64[:, :cols])
+        cpu_s = time.perf_counter() - t1
+        ad = torch.from_numpy(a_o).to(dev)
+        ld = torch.tensor([lmax_o], dtype=torch.float64, device=dev)
+        Yg = asc.cheb_filter(G, ld, ad, R, Y)[:, :cols].cpu().numpy().astype(np.float64)
+        err["f32"] = float(np.linalg.norm(Yg - Yref) / np.linalg.norm(Yref))
+        if ms_bf16 is not None:
+            Ybref = cb.cheb_filter(n, g.row_ptr, g.col_idx, None, lmax_o, a_o, Rbf64[:, :cols])
+            Ygb = asc.cheb_filter(G, ld, ad, Rb, Y)[:, :cols].cpu().numpy().astype(np.float64)
+            err["bf16_vs_fp64_on_bf16_R"] = float(np.linalg.norm(Ygb - Ybref) / np.linalg.norm(Ybref))
+            err["bf16_vs_fp64_on_fp64_R"] = float(np.linalg.norm(Ygb - Yref) / np.linalg.norm(Yref))
+        err["sample"] = f"columns 0..{cols - 1} of R, lambda_max = oracle Lanczos (40 it), lambda_c = 0.17 lambda_max"
+        if not args.no_cpu_baseline:
+            ms_cpu_full = cpu_s * 1e3 * (r / cols)  # the recurrence is independent per column
+            cpu = {"value": p * bs32 / (ms_cpu_full * 1e-3) / 1e9, "unit": "GB/s", "cores": cb.num_threads(),
+                   "kind": "oracle", "ms_per_filter_extrapolated": ms_cpu_full,
+                   "sample": f"FP64 C/OpenMP recurrence on {cols} of {r} columns, full graph, p={p}, "
+                             f"{cpu_s:.1f} s; scaled by {r}/{cols} to one filter"}
+
+    steps_per_filter = p
+    line = {
+        "metric": "Chebyshev-filter SpMM HBM GB/s + ms/filter (fwd, fwd+bwd) at err vs FP64",
+        "value": round(gbs32, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": n, "nnz": nnz, "r": r, "p": p, "k": k,
+                   "dichotomy_steps": steps_dich, "kmeans_iters": km_iters},
+        "ms_per_filter_fwd": round(ms_f32, 4),
+        "ms_per_filter_fwd_bwd": None,
+        "err_vs_fp64": err,
+        "bf16": None if ms_bf16 is None else {"ms_per_filter_fwd": round(ms_bf16, 4), "gbs": round(gbs16, 2)},
+        "components_ms": {k_: round(v, 4) for k_, v in comp.items()},
+        "lambda_max": lmax_h,
+        "lambda_k_est": lam_k_h,
+        "roofline": {"bound": "hbm", "achieved": round(gbs32, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs32 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "cheb_step", "unit_bytes": bs32, "units_per_filter": steps_per_filter},
+        "cpu_baseline": cpu,
+        "gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

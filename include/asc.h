@@ -1,0 +1,212 @@
+/*
+ * asc.h -- C ABI of the MI355X (gfx950) hot path of accelerated spectral
+ * clustering by graph filtering of random signals (Tremblay, Puy, Borgnat,
+ * Gribonval & Vandergheynst, ICASSP 2016).
+ *
+ * Problem statement followed (algorithm of Sec. 4.1): given an undirected
+ * weighted graph W (Sec. 2.1) and a number of clusters k,
+ *   1. estimate lambda_N, the largest eigenvalue of L = S - W;
+ *   2. estimate lambda_k by counting eigenvalues below trial cut-offs with
+ *      filtered random signals and bisecting on [0, lambda_N] (Sec. 3.2);
+ *   3. build the order-p polynomial approximation of the ideal low-pass
+ *      h_{lambda_k} (Eq. ideal, Sec. 2.4);
+ *   4-5. filter eta = r random signals, row i of the result is node i's feature
+ *      vector (Sec. 3.1);
+ *   6. run k-means on the features.
+ * The polynomial is a Chebyshev expansion on [0, lambda_max] with Jackson
+ * damping: p(x) = sum_{j=0..p} a_j T_j(x), x = 2 lambda / lambda_max - 1,
+ * a_j = g_j c_j, where c_j are the exact Chebyshev coefficients of the step
+ * 1[x <= x_c] with c_0 NOT halved, and g_j the Jackson factors.  Filtering
+ * evaluates Y = sum_j a_j T_j(Lt) R, Lt = (2/lambda_max) L - I, by the
+ * three-term recurrence T_{j+1} = 2 Lt T_j - T_{j-1}.
+ *
+ * Conventions (every entry point):
+ *  - Pointers are DEVICE pointers unless the name ends in _host.  All buffers
+ *    are owned by the caller; the library never allocates device memory.
+ *    Work that needs scratch takes (ws, ws_bytes) sized by the matching
+ *    *_workspace() query; ws must be 256-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued on it in order; only arguments ending in _host synchronise the
+ *    stream.  Without _host outputs a call never synchronises and may be
+ *    captured into a HIP graph (no memset nodes are recorded).
+ *  - Signal blocks are row-major n x r with leading dimension ld (elements):
+ *    row i, column c at base[i*ld + c].  float32 blocks need ld % 4 == 0 and
+ *    16-byte aligned base; bfloat16 blocks ld % 8 == 0 and 16-byte alignment.
+ *    r may be any value >= 1 (ragged column tails are masked).
+ *  - Arguments are validated before any launch; a violation returns
+ *    ASC_ERR_INVALID and launches nothing.  A HIP launch error returns
+ *    ASC_ERR_HIP.  Outputs are unspecified after an error, but no write ever
+ *    leaves the buffers described here.  asc_last_error() describes the most
+ *    recent failure of the calling thread.
+ *  - The only process-wide state is the tuning table (asc_tune_*).
+ */
+#ifndef ASC_H
+#define ASC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASC_ABI_VERSION 1
+
+typedef enum {
+    ASC_OK = 0,
+    ASC_ERR_INVALID = 1,        /* bad argument, shape, alignment or graph       */
+    ASC_ERR_WORKSPACE = 2,      /* ws NULL, misaligned or smaller than required  */
+    ASC_ERR_HIP = 3,            /* a HIP runtime call or launch failed           */
+    ASC_ERR_NONFINITE = 4,      /* NaN/Inf met in a checked result               */
+    ASC_ERR_LMAX_TOO_SMALL = 5  /* lambda_max below lambda_N: recurrence grows   */
+} asc_status;
+
+typedef enum { ASC_F32 = 0, ASC_BF16 = 1 } asc_dtype;
+
+/* Device-side health flags (bit set), readable with asc_read_flags. */
+#define ASC_FLAG_NONFINITE 1u
+#define ASC_FLAG_GROWTH 2u      /* |T_j R|_F > 1.5 |R|_F: lambda_max too small */
+#define ASC_FLAG_BAD_GRAPH 4u
+
+/* Undirected weighted graph W (Sec. 2.1) in CSR, both (i,j) and (j,i) stored.
+ * row_ptr[n+1] (row_ptr[0] = 0, row_ptr[n] = nnz < 2^31), col_idx[nnz]
+ * strictly increasing inside a row, no self-loops; w[nnz] finite, >= 0 and
+ * symmetric (W_ij = W_ji), or NULL for unit weights.  strength[n] holds
+ * s_i = sum_j W_ij in float64 and is filled by asc_graph_prepare; every
+ * other call reads it.  L = S - W is never formed. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const float *w;
+    const double *strength;
+} asc_graph;
+
+int asc_abi_version(void);
+/* Text of the calling thread's last error ("" if none); never NULL. */
+const char *asc_last_error(void);
+
+/* Node strengths s_i = sum_{j != i} W_ij of Sec. 2.1 (float64, summed in
+ * row order).  strength[n] is written.  validate != 0 additionally checks the
+ * CSR invariants above, the weights and the symmetry of W on the device
+ * (needs ws of asc_graph_prepare_workspace bytes, else ws may be NULL),
+ * synchronises, and returns ASC_ERR_INVALID if any check fails. */
+size_t asc_graph_prepare_workspace(int64_t n, int validate);
+asc_status asc_graph_prepare(const asc_graph *g, double *strength, int validate, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Step 1 of the algorithm (Sec. 4.1): an upper estimate of lambda_N.
+ * Lanczos in float64 from the start vector v0[n] (not normalised; any
+ * non-zero vector) for `iters` steps (stops early on breakdown), then
+ * lmax = min(1.01 * largest Ritz value, 2 max_i s_i) (Gershgorin bound).
+ * Writes lmax[1] (device); lmax_host (may be NULL) synchronises and copies it.
+ * iters in [1, 4096]. */
+size_t asc_lmax_workspace(int64_t n, int iters);
+asc_status asc_lmax_estimate(const asc_graph *g, const double *v0, int iters, double *lmax,
+                             double *lmax_host, void *ws, size_t ws_bytes, void *stream);
+
+/* Step 3 (Sec. 2.4, Sec. 4.1): coefficients of the ideal low-pass h_{lambda_c}
+ * (Eq. ideal) for n_cut cut-offs lambda_c[n_cut] on [0, lmax[0]]:
+ * x_c = clip(2 lambda_c/lmax - 1, -1, 1), theta = acos x_c,
+ * c_0 = 1 - theta/pi, c_j = -2 sin(j theta)/(j pi); jackson != 0 multiplies by
+ * g_j = [(p+2-j) cos(j a) + sin(j a) cot a]/(p+2), a = pi/(p+2).
+ * Writes coeffs[n_cut][p+1] (float64, computed on the device). p in [0, 100000]. */
+asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax, int p, int jackson,
+                           double *coeffs, void *stream);
+
+/* Steps 4-5 (Sec. 3.1, Sec. 2.4): Y = sum_{j=0..p} a_j T_j(Lt) R.
+ * R: n x r block of dtype sig (float32 or bfloat16), leading dim ldr.
+ * Y: n x r float32, leading dim ldy, must not overlap R.  coeffs[p+1] float64
+ * (device), lmax[1] float64 (device).  Signal states are stored in `sig`,
+ * arithmetic and the accumulation of Y are float32.
+ * ckpt (may be NULL): receives the recurrence checkpoints used by
+ * asc_cheb_filter_bwd, ckpt_stride >= 2; size from asc_ckpt_bytes.
+ * The call also computes |T_0|_F and |T_p|_F and raises ASC_FLAG_GROWTH /
+ * ASC_FLAG_NONFINITE in the workspace flags (asc_read_flags). */
+size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p);
+size_t asc_ckpt_bytes(int64_t n, int64_t r, asc_dtype sig, int p, int ckpt_stride);
+asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, const double *coeffs, int p,
+                           const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
+                           void *ckpt, int ckpt_stride, void *ws, size_t ws_bytes, void *stream);
+
+/* Sec. 3.2: Chebyshev moments mu_j = <R, T_j(Lt) R>_F, j = 0..p (float64,
+ * deterministic fixed-order reductions), from ceil(p/2) recurrence steps
+ * using mu_{2j} = 2 |T_j R|^2 - mu_0 and mu_{2j+1} = 2 <T_{j+1} R, T_j R> - mu_1
+ * (valid because Lt is symmetric).  The eigenvalue count below lambda_c is
+ * then sum_j a_j(lambda_c) mu_j.  Writes mu[p+1]. */
+size_t asc_moments_workspace(int64_t n, int64_t r, asc_dtype sig, int p);
+asc_status asc_cheb_moments(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig,
+                            int64_t r, int64_t ldr, double *mu, void *ws, size_t ws_bytes, void *stream);
+
+/* Sec. 3.2 dichotomy on [0, lmax]: lo = 0, hi = lmax; `steps` times
+ * mid = (lo+hi)/2, count = sum_j a_j(mid) mu_j, hi = mid if count >= k - 1/2
+ * else lo = mid.  Writes lambda_k[1] = hi and traj[steps][2] = (mid, count).
+ * Runs on the device in float64. */
+asc_status asc_eigcount_dichotomy(const double *mu, int p, const double *lmax, int k, int steps, int jackson,
+                                  double *lambda_k, double *traj, void *stream);
+
+/* Step 2 of Sec. 4.1: lambda_k estimate from random signals R.  literal == 0:
+ * one moment pass (asc_cheb_moments) then the dichotomy; literal != 0: one
+ * filter pass per trial cut-off with count = <R, Y_mid>_F.  Same outputs as
+ * asc_eigcount_dichotomy. */
+size_t asc_eigcount_workspace(int64_t n, int64_t r, asc_dtype sig, int p, int steps, int literal);
+asc_status asc_eigcount_lambda_k(const asc_graph *g, const double *lmax, int k, int p, int steps, int literal,
+                                 const void *R, asc_dtype sig, int64_t r, int64_t ldr, double *lambda_k,
+                                 double *traj, void *ws, size_t ws_bytes, void *stream);
+
+/* Row normalisation of the features (footnote of Sec. 2.1): y_i <- y_i/|y_i|,
+ * zero rows stay zero.  In place on Y (n x r float32, ldy); norms[n] (may be
+ * NULL) receives |y_i| (float32, accumulated in float64). */
+asc_status asc_normalize_features(float *Y, int64_t n, int64_t r, int64_t ldy, float *norms, void *stream);
+
+/* Step 6 (Sec. 4.1), k-means with Euclidean distance.
+ * init_rows: C[c] = F[rows[c]] for c < k (rows[k] int32 on the device).
+ * assign: labels_i = argmin_c sum_col (F_ic - C_cc)^2 evaluated in float64
+ *   column by column in order (no fused multiply-add), lowest c on ties;
+ *   dist2[n] (may be NULL) gets the minimum as float32.  k in [1, 1024],
+ *   r <= 4096.
+ * update: C[c] = mean of the members of c (float64 sums in a fixed order,
+ *   rounded to float32); an empty cluster keeps its previous centroid;
+ *   counts[k] (int64, may be NULL) gets the member counts.
+ * F: n x r float32 (ldf); C: k x r float32 contiguous. */
+asc_status asc_kmeans_init_rows(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *rows, int k,
+                                float *C, void *stream);
+asc_status asc_kmeans_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k,
+                             int32_t *labels, float *dist2, void *stream);
+size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k);
+asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k,
+                             float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Kernel configuration of the recurrence step, kept in a process-wide table
+ * keyed by (n, nnz, r, sig); calls on a graph without an entry use the
+ * default (slice width = the smallest of 8/16/32 float32 or 16/32/64 bfloat16
+ * columns that covers r, variant 0).
+ *   slice_cols: columns processed per pass (float32: 8, 16, 32, 64;
+ *               bfloat16: 16, 32, 64, 128); 0 in asc_tune_set removes the
+ *               entry.
+ *   variant:    0 = plain loads; 1 = non-temporal hints on the streamed
+ *               arrays (CSR, T_{j-1}, Y) so that the gathered block stays cached.
+ * asc_autotune_filter times every candidate on the caller's graph and signals
+ * for probe_steps recurrence steps (Y and ws are scratch; needs ws of
+ * asc_filter_workspace(n, r, sig, 1) bytes), records the fastest and returns
+ * it.  It synchronises the stream.  asc_tune_save / asc_tune_load write and
+ * read the table as JSON (one entry per line).  The table is guarded by a
+ * mutex. */
+asc_status asc_tune_set(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int slice_cols, int variant);
+asc_status asc_tune_get(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int *slice_cols, int *variant);
+asc_status asc_tune_save(const char *path);
+asc_status asc_tune_load(const char *path);
+asc_status asc_autotune_filter(const asc_graph *g, const double *lmax, const void *R, asc_dtype sig, int64_t r,
+                               int64_t ldr, float *Y, int64_t ldy, int probe_steps, void *ws, size_t ws_bytes,
+                               int *best_slice_cols, int *best_variant, float *best_ms_per_step, void *stream);
+
+/* Health flags raised by the last filter / moment pass that used ws.
+ * Synchronises the stream; flags_host gets ASC_FLAG_* bits.  Returns
+ * ASC_ERR_LMAX_TOO_SMALL or ASC_ERR_NONFINITE if the matching flag is set. */
+asc_status asc_read_flags(const void *ws, uint32_t *flags_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASC_H */

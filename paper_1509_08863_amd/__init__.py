@@ -1,0 +1,239 @@
+"""Accelerated spectral clustering by graph filtering of random signals
+(Tremblay et al., ICASSP 2016) on MI355X: Python binding of libasc.
+
+Thin argument marshalling over the C ABI of include/asc.h: every function has
+the name of its C entry point without the ``asc_`` prefix, takes torch tensors
+on the GPU, allocates outputs and workspaces with torch (device memory and
+streams are torch's; all arithmetic runs in the HIP kernels) and enqueues the
+work on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import AscError, ASC_F32, ASC_BF16  # noqa: F401
+
+__all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filter", "cheb_moments",
+           "eigcount_dichotomy", "eigcount_lambda_k", "normalize_features", "kmeans_init_rows",
+           "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
+           "tune_save", "tune_load", "autotune_filter"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return ASC_F32
+    if t.dtype == torch.bfloat16:
+        return ASC_BF16
+    raise TypeError(f"signal block must be float32 or bfloat16, got {t.dtype}")
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("blocks must be 2-D with unit column stride")
+    return t.stride(0)
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A 256-byte aligned device buffer of at least nbytes (torch-allocated)."""
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(int(nbytes), 1)]
+
+
+class Graph:
+    """CSR graph W on the device plus its float64 strengths (asc_graph)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, w: torch.Tensor | None,
+                 strength: torch.Tensor):
+        self.row_ptr, self.col_idx, self.w, self.strength = row_ptr, col_idx, w, strength
+        self.n = row_ptr.numel() - 1
+        self.nnz = col_idx.numel()
+        self._c = _abi.asc_graph(self.n, self.nnz, row_ptr.data_ptr(), col_idx.data_ptr() if self.nnz else None,
+                                 None if w is None else w.data_ptr(), strength.data_ptr())
+
+    @property
+    def device(self):
+        return self.row_ptr.device
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+    def with_weights(self, w: torch.Tensor | None) -> "Graph":
+        """Same pattern with other weights (strengths must be re-prepared)."""
+        return graph_prepare(self.row_ptr, self.col_idx, w)
+
+
+def graph_prepare(row_ptr: torch.Tensor, col_idx: torch.Tensor, w: torch.Tensor | None = None,
+                  validate: bool = False) -> Graph:
+    L = _abi.lib()
+    n = row_ptr.numel() - 1
+    strength = torch.empty(n, dtype=torch.float64, device=row_ptr.device)
+    g = Graph(row_ptr, col_idx, w, strength)
+    ws = workspace(L.asc_graph_prepare_workspace(n, int(validate)), row_ptr.device) if validate else None
+    _abi.check(L.asc_graph_prepare(g.c(), _ptr(strength), int(validate), _ptr(ws),
+                                   0 if ws is None else ws.numel(), _stream()))
+    return g
+
+
+def lmax_estimate(g: Graph, v0: torch.Tensor, iters: int = 60, host: bool = False):
+    L = _abi.lib()
+    out = torch.empty(1, dtype=torch.float64, device=g.device)
+    ws = workspace(L.asc_lmax_workspace(g.n, iters), g.device)
+    h = ctypes.c_double(0.0)
+    _abi.check(L.asc_lmax_estimate(g.c(), _ptr(v0), iters, _ptr(out), ctypes.byref(h) if host else None,
+                                   _ptr(ws), ws.numel(), _stream()))
+    return (out, h.value) if host else out
+
+
+def cheb_coeffs(lambda_c: torch.Tensor, lmax: torch.Tensor, p: int, jackson: bool = True) -> torch.Tensor:
+    lambda_c = lambda_c.reshape(-1)
+    out = torch.empty(lambda_c.numel(), p + 1, dtype=torch.float64, device=lambda_c.device)
+    _abi.check(_abi.lib().asc_cheb_coeffs(_ptr(lambda_c), lambda_c.numel(), _ptr(lmax), p, int(jackson),
+                                          _ptr(out), _stream()))
+    return out
+
+
+def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, Y: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None) -> torch.Tensor:
+    L = _abi.lib()
+    coeffs = coeffs.reshape(-1)
+    p = coeffs.numel() - 1
+    n, r = R.shape
+    if Y is None:
+        ldy = (r + 3) // 4 * 4
+        Y = torch.empty(n, ldy, dtype=torch.float32, device=R.device)[:, :r]
+    dt = _dtype_code(R)
+    need = L.asc_filter_workspace(n, r, dt, p)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, R.device)
+    _abi.check(L.asc_cheb_filter(g.c(), _ptr(lmax), _ptr(coeffs), p, _ptr(R), dt, r, _ld(R), _ptr(Y), _ld(Y),
+                                 None, 0, _ptr(ws), ws.numel(), _stream()))
+    cheb_filter.last_ws = ws
+    return Y
+
+
+def cheb_moments(g: Graph, lmax: torch.Tensor, p: int, R: torch.Tensor) -> torch.Tensor:
+    L = _abi.lib()
+    n, r = R.shape
+    dt = _dtype_code(R)
+    mu = torch.empty(p + 1, dtype=torch.float64, device=R.device)
+    ws = workspace(L.asc_moments_workspace(n, r, dt, p), R.device)
+    _abi.check(L.asc_cheb_moments(g.c(), _ptr(lmax), p, _ptr(R), dt, r, _ld(R), _ptr(mu), _ptr(ws), ws.numel(),
+                                  _stream()))
+    cheb_moments.last_ws = ws
+    return mu
+
+
+def eigcount_dichotomy(mu: torch.Tensor, lmax: torch.Tensor, k: int, steps: int, jackson: bool = True):
+    lam = torch.empty(1, dtype=torch.float64, device=mu.device)
+    traj = torch.empty(max(steps, 1), 2, dtype=torch.float64, device=mu.device)
+    _abi.check(_abi.lib().asc_eigcount_dichotomy(_ptr(mu), mu.numel() - 1, _ptr(lmax), k, steps, int(jackson),
+                                                 _ptr(lam), _ptr(traj), _stream()))
+    return lam, traj[:steps]
+
+
+def eigcount_lambda_k(g: Graph, lmax: torch.Tensor, k: int, p: int, steps: int, R: torch.Tensor,
+                      literal: bool = False):
+    L = _abi.lib()
+    n, r = R.shape
+    dt = _dtype_code(R)
+    lam = torch.empty(1, dtype=torch.float64, device=R.device)
+    traj = torch.empty(max(steps, 1), 2, dtype=torch.float64, device=R.device)
+    ws = workspace(L.asc_eigcount_workspace(n, r, dt, p, steps, int(literal)), R.device)
+    _abi.check(L.asc_eigcount_lambda_k(g.c(), _ptr(lmax), k, p, steps, int(literal), _ptr(R), dt, r, _ld(R),
+                                       _ptr(lam), _ptr(traj), _ptr(ws), ws.numel(), _stream()))
+    eigcount_lambda_k.last_ws = ws
+    return lam, traj[:steps]
+
+
+def normalize_features(Y: torch.Tensor, want_norms: bool = True):
+    n, r = Y.shape
+    norms = torch.empty(n, dtype=torch.float32, device=Y.device) if want_norms else None
+    _abi.check(_abi.lib().asc_normalize_features(_ptr(Y), n, r, _ld(Y), _ptr(norms), _stream()))
+    return norms
+
+
+def kmeans_init_rows(F: torch.Tensor, rows: torch.Tensor) -> torch.Tensor:
+    n, r = F.shape
+    k = rows.numel()
+    C = torch.empty(k, r, dtype=torch.float32, device=F.device)
+    _abi.check(_abi.lib().asc_kmeans_init_rows(_ptr(F), n, r, _ld(F), _ptr(rows), k, _ptr(C), _stream()))
+    return C
+
+
+def kmeans_assign(F: torch.Tensor, C: torch.Tensor):
+    n, r = F.shape
+    k = C.shape[0]
+    labels = torch.empty(n, dtype=torch.int32, device=F.device)
+    dist2 = torch.empty(n, dtype=torch.float32, device=F.device)
+    _abi.check(_abi.lib().asc_kmeans_assign(_ptr(F), n, r, _ld(F), _ptr(C.contiguous()), k, _ptr(labels),
+                                            _ptr(dist2), _stream()))
+    return labels, dist2
+
+
+def kmeans_update(F: torch.Tensor, labels: torch.Tensor, C: torch.Tensor, ws: torch.Tensor | None = None):
+    """Updates C (k x r float32, contiguous) in place; returns the member counts."""
+    L = _abi.lib()
+    n, r = F.shape
+    k = C.shape[0]
+    assert C.is_contiguous()
+    counts = torch.empty(k, dtype=torch.int64, device=F.device)
+    need = L.asc_kmeans_update_workspace(n, r, k)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, F.device)
+    _abi.check(L.asc_kmeans_update(_ptr(F), n, r, _ld(F), _ptr(labels), k, _ptr(C), _ptr(counts), _ptr(ws),
+                                   ws.numel(), _stream()))
+    return counts
+
+
+def read_flags(ws: torch.Tensor, raise_on_error: bool = True) -> int:
+    f = ctypes.c_uint32(0)
+    st = _abi.lib().asc_read_flags(_ptr(ws), ctypes.byref(f), _stream())
+    if raise_on_error:
+        _abi.check(st)
+    return int(f.value)
+
+
+def tune_set(g: Graph, r: int, dtype: torch.dtype, slice_cols: int, variant: int = 0) -> None:
+    dt = ASC_F32 if dtype == torch.float32 else ASC_BF16
+    _abi.check(_abi.lib().asc_tune_set(g.n, g.nnz, r, dt, slice_cols, variant))
+
+
+def tune_get(g: Graph, r: int, dtype: torch.dtype):
+    dt = ASC_F32 if dtype == torch.float32 else ASC_BF16
+    rs, var = ctypes.c_int(0), ctypes.c_int(0)
+    _abi.check(_abi.lib().asc_tune_get(g.n, g.nnz, r, dt, ctypes.byref(rs), ctypes.byref(var)))
+    return rs.value, var.value
+
+
+def tune_save(path: str) -> None:
+    _abi.check(_abi.lib().asc_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _abi.check(_abi.lib().asc_tune_load(path.encode()))
+
+
+def autotune_filter(g: Graph, lmax: torch.Tensor, R: torch.Tensor, probe_steps: int = 3):
+    """Times every (slice width, variant) candidate; returns (slice_cols, variant, ms per step)."""
+    L = _abi.lib()
+    n, r = R.shape
+    dt = _dtype_code(R)
+    Y = torch.empty(n, (r + 3) // 4 * 4, dtype=torch.float32, device=R.device)[:, :r]
+    ws = workspace(L.asc_filter_workspace(n, r, dt, 1), R.device)
+    rs, var, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0)
+    _abi.check(L.asc_autotune_filter(g.c(), _ptr(lmax), _ptr(R), dt, r, _ld(R), _ptr(Y), _ld(Y), probe_steps,
+                                     _ptr(ws), ws.numel(), ctypes.byref(rs), ctypes.byref(var), ctypes.byref(ms),
+                                     _stream()))
+    return rs.value, var.value, ms.value

@@ -1,0 +1,95 @@
+"""ctypes declarations of libasc.so (include/asc.h).  Loading fails loudly if
+the library has not been built: there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasc.so")
+
+ASC_OK = 0
+ASC_ERR_INVALID = 1
+ASC_ERR_WORKSPACE = 2
+ASC_ERR_HIP = 3
+ASC_ERR_NONFINITE = 4
+ASC_ERR_LMAX_TOO_SMALL = 5
+ASC_F32 = 0
+ASC_BF16 = 1
+ASC_FLAG_NONFINITE = 1
+ASC_FLAG_GROWTH = 2
+
+STATUS_NAMES = {0: "ASC_OK", 1: "ASC_ERR_INVALID", 2: "ASC_ERR_WORKSPACE", 3: "ASC_ERR_HIP",
+                4: "ASC_ERR_NONFINITE", 5: "ASC_ERR_LMAX_TOO_SMALL"}
+
+
+class AscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class asc_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("w", ctypes.c_void_p), ("strength", ctypes.c_void_p)]
+
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int
+D = ctypes.c_double
+SZ = ctypes.c_size_t
+GP = ctypes.POINTER(asc_graph)
+
+# name -> (restype, argtypes); one line per entry point of include/asc.h
+SIGNATURES = {
+    "asc_abi_version": (ctypes.c_int, []),
+    "asc_last_error": (ctypes.c_char_p, []),
+    "asc_graph_prepare_workspace": (SZ, [I64, I32]),
+    "asc_graph_prepare": (I32, [GP, P, I32, P, SZ, P]),
+    "asc_lmax_workspace": (SZ, [I64, I32]),
+    "asc_lmax_estimate": (I32, [GP, P, I32, P, P, P, SZ, P]),
+    "asc_cheb_coeffs": (I32, [P, I32, P, I32, I32, P, P]),
+    "asc_filter_workspace": (SZ, [I64, I64, I32, I32]),
+    "asc_ckpt_bytes": (SZ, [I64, I64, I32, I32, I32]),
+    "asc_cheb_filter": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I64, P, I32, P, SZ, P]),
+    "asc_moments_workspace": (SZ, [I64, I64, I32, I32]),
+    "asc_cheb_moments": (I32, [GP, P, I32, P, I32, I64, I64, P, P, SZ, P]),
+    "asc_eigcount_dichotomy": (I32, [P, I32, P, I32, I32, I32, P, P, P]),
+    "asc_eigcount_workspace": (SZ, [I64, I64, I32, I32, I32, I32]),
+    "asc_eigcount_lambda_k": (I32, [GP, P, I32, I32, I32, I32, P, I32, I64, I64, P, P, P, SZ, P]),
+    "asc_normalize_features": (I32, [P, I64, I64, I64, P, P]),
+    "asc_kmeans_init_rows": (I32, [P, I64, I64, I64, P, I32, P, P]),
+    "asc_kmeans_assign": (I32, [P, I64, I64, I64, P, I32, P, P, P]),
+    "asc_kmeans_update_workspace": (SZ, [I64, I64, I32]),
+    "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
+    "asc_read_flags": (I32, [P, ctypes.POINTER(ctypes.c_uint32), P]),
+    "asc_tune_set": (I32, [I64, I64, I64, I32, I32, I32]),
+    "asc_tune_get": (I32, [I64, I64, I64, I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "asc_tune_save": (I32, [ctypes.c_char_p]),
+    "asc_tune_load": (I32, [ctypes.c_char_p]),
+    "asc_autotune_filter": (I32, [GP, P, P, I32, I64, I64, P, I64, I32, P, SZ, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), P]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_08863_amd.build` "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != ASC_OK:
+        raise AscError(status, lib().asc_last_error().decode(errors="replace"))

@@ -1,0 +1,1116 @@
+// Polynomial low-pass filtering of random signals (Sec. 2.4, Sec. 3.1, steps
+// 3-5 of the algorithm in Sec. 4.1) and the Chebyshev moments behind the
+// eigenvalue count of Sec. 3.2.
+//
+// Data layout.  The caller's blocks are row-major n x r.  Internally the
+// columns are processed in slices of RS columns (RS = lanes-per-row x 16 bytes
+// of elements); each slice runs its whole recurrence before the next one, so
+// the block that is gathered at random rows (T_j of the slice, n x RS) stays
+// small enough to live in the 256 MB Infinity Cache.  Slice states live in
+// "panels": n x RS, contiguous, zero-padded past column r.  Two panels
+// suffice because T_{j+1} overwrites T_{j-1} row by row (row i of T_{j-1} is
+// read only by the lanes that write row i of T_{j+1}).
+//
+// One recurrence step (kernel cheb_step):
+//   T_{j+1}[i] = d_i T_j[i] + beta sum_k w_ik T_j[k] - T_{j-1}[i],
+//   d_i = 4 s_i / lmax - 2, beta = -4 / lmax   (= 2 Lt T_j - T_{j-1}),
+//   Y[i] += a_{j+1} T_{j+1}[i]                  (fused, float32),
+// with LPR lanes of a wavefront per row (64/LPR rows per wavefront), each
+// lane owning 16 bytes of the row: the gather of T_j[k] is one coalesced
+// 16*LPR-byte segment per neighbour.  Optional float64 partial sums per block
+// (|T_j|^2, <T_{j+1}, T_j>, |T_{j+1}|^2) feed the moments and the growth check.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+namespace asc {
+
+// process-wide tuning table: kernel configuration per (n, nnz, r, dtype)
+struct TuneKey {
+    int64_t n, nnz, r;
+    int dt;
+    bool operator==(const TuneKey &o) const { return n == o.n && nnz == o.nnz && r == o.r && dt == o.dt; }
+};
+struct TuneEntry {
+    TuneKey key;
+    int rs;       // slice width (columns)
+    int var;      // kernel variant bits
+    float ms;     // measured time of one recurrence step over all columns
+};
+std::mutex &tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+std::vector<TuneEntry> &tune_table() {
+    static std::vector<TuneEntry> t;
+    return t;
+}
+
+namespace {
+
+constexpr int NT = 256;          // threads per block (4 wavefronts)
+constexpr int kMaxGrid = 8192;   // cap of blocks per step launch (grid-stride beyond)
+constexpr unsigned M_FIRST = 1u;  // step 0: T_1 = Lt T_0 (there is no T_{-1})
+constexpr unsigned M_YACC = 2u;   // Y += a_{j+1} T_{j+1}; with M_FIRST: Y = a_0 T_0 + a_1 T_1
+constexpr unsigned M_PART = 4u;   // write float64 partial sums
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// storage element types: float (4 per 16 B) and bfloat16 bits (8 per 16 B)
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+template <typename TS> struct St;
+template <> struct St<float> { static constexpr int VN = 4; typedef v4f raw; };
+template <> struct St<uint16_t> { static constexpr int VN = 8; typedef v4u raw; };
+
+// loads/stores with an optional non-temporal hint (streamed data that is not
+// re-read in this step: CSR arrays, T_{j-1}, Y)
+template <bool NTH, typename T>
+__device__ __forceinline__ T ldx(const T *p) {
+    if constexpr (NTH) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NTH, typename T>
+__device__ __forceinline__ void stx(T *p, T v) {
+    if constexpr (NTH) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <bool NTH = false>
+__device__ __forceinline__ v4f ldraw(const float *p) { return ldx<NTH>(reinterpret_cast<const v4f *>(p)); }
+template <bool NTH = false>
+__device__ __forceinline__ v4u ldraw(const uint16_t *p) { return ldx<NTH>(reinterpret_cast<const v4u *>(p)); }
+
+__device__ __forceinline__ void unpack(const v4f &x, float (&v)[4]) {
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void unpack(const v4u &x, float (&v)[8]) {
+    v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
+    v[4] = bf16_lo(x.z); v[5] = bf16_hi(x.z); v[6] = bf16_lo(x.w); v[7] = bf16_hi(x.w);
+}
+// acc += w * x (one fused multiply-add per element, in element order)
+__device__ __forceinline__ void fma_raw(float (&acc)[4], float w, const v4f &x) {
+    acc[0] = fmaf(w, x.x, acc[0]); acc[1] = fmaf(w, x.y, acc[1]);
+    acc[2] = fmaf(w, x.z, acc[2]); acc[3] = fmaf(w, x.w, acc[3]);
+}
+__device__ __forceinline__ void fma_raw(float (&acc)[8], float w, const v4u &x) {
+    acc[0] = fmaf(w, bf16_lo(x.x), acc[0]); acc[1] = fmaf(w, bf16_hi(x.x), acc[1]);
+    acc[2] = fmaf(w, bf16_lo(x.y), acc[2]); acc[3] = fmaf(w, bf16_hi(x.y), acc[3]);
+    acc[4] = fmaf(w, bf16_lo(x.z), acc[4]); acc[5] = fmaf(w, bf16_hi(x.z), acc[5]);
+    acc[6] = fmaf(w, bf16_lo(x.w), acc[6]); acc[7] = fmaf(w, bf16_hi(x.w), acc[7]);
+}
+// store v rounded to the storage type; `r` receives the stored values
+__device__ __forceinline__ void st16(float *p, const float (&v)[4], float (&r)[4]) {
+    v4f x = {v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<v4f *>(p) = x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = v[q];
+}
+__device__ __forceinline__ void st16(uint16_t *p, const float (&v)[8], float (&r)[8]) {
+    v4u x;
+    x.x = pack_bf16x2(v[0], v[1]); x.y = pack_bf16x2(v[2], v[3]);
+    x.z = pack_bf16x2(v[4], v[5]); x.w = pack_bf16x2(v[6], v[7]);
+    *reinterpret_cast<v4u *>(p) = x;
+    unpack(x, r);
+}
+
+struct StepArgs {
+    int64_t n;
+    const int32_t *rp;
+    const int32_t *ci;
+    const float *w;        // nullptr: unit weights
+    const float *diag;     // d_i (float32)
+    const float *beta;     // beta[0] = -4/lmax
+    const void *cur;       // panel T_j
+    const void *prev;      // panel T_{j-1} (unused with M_FIRST)
+    void *out;             // panel T_{j+1} (may equal prev)
+    float *Y;              // caller block (slice columns c0..)
+    int64_t ldy, c0, r;
+    const double *coeffs;  // a_0..a_p
+    int j;                 // this step produces T_{j+1}
+    double *partials;      // [gridDim.x][3]
+};
+
+// Kernel variants (VAR bits): bit 0 = non-temporal hints on the streamed
+// arrays.  The neighbour loop gathers U rows per iteration and prefetches the
+// next U column indices / weights while the gathers are in flight.
+template <typename TS, int LPR, unsigned MODE, unsigned VAR>
+__global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
+    constexpr bool NTH = (VAR & 1u) != 0;
+    constexpr int VN = St<TS>::VN;
+    constexpr int RS = LPR * VN;
+    constexpr int RPW = 64 / LPR;
+    constexpr int ROWS = RPW * (NT / 64);
+    constexpr int U = 8;
+    typedef typename St<TS>::raw raw_t;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int t = lane % LPR;
+    const int sub = lane / LPR;
+    const TS *__restrict__ cur = static_cast<const TS *>(A.cur);
+    const TS *__restrict__ prv = static_cast<const TS *>(A.prev);
+    TS *__restrict__ out = static_cast<TS *>(A.out);
+    const float beta = A.beta[0];
+    const float aj1 = (MODE & M_YACC) ? (float)A.coeffs[A.j + 1] : 0.0f;
+    const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)A.coeffs[0] : 0.0f;
+    const bool weighted = A.w != nullptr;
+    double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
+    const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
+        if (row >= A.n) continue;
+        const int32_t e0 = ldx<NTH>(A.rp + row), e1 = ldx<NTH>(A.rp + row + 1);
+        float acc[VN];
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
+        const TS *base = cur + t * VN;
+        // padding slots gather the row itself with weight 0
+        int32_t kn[U];
+        float wn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            kn[u] = (int32_t)row;
+            wn[u] = 0.0f;
+            if (e0 + u < e1) {
+                kn[u] = ldx<NTH>(A.ci + e0 + u);
+                wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
+            }
+        }
+        for (int32_t e = e0; e < e1; e += U) {
+            int32_t kc[U];
+            float wc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kc[u] = kn[u];
+                wc[u] = wn[u];
+            }
+            raw_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+            const int32_t en = e + U;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kn[u] = (int32_t)row;
+                wn[u] = 0.0f;
+                if (en + u < e1) {
+                    kn[u] = ldx<NTH>(A.ci + en + u);
+                    wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+        }
+        float own[VN], nxt[VN], stv[VN];
+        unpack(ldraw(cur + row * RS + t * VN), own);
+        const float d = ldx<NTH>(A.diag + row);
+        if (MODE & M_FIRST) {
+#pragma unroll
+            for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
+        } else {
+            float pv[VN];
+            unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
+#pragma unroll
+            for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
+        }
+        st16(out + row * RS + t * VN, nxt, stv);
+        if (MODE & M_YACC) {
+            const int64_t cbase = A.c0 + (int64_t)t * VN;
+            float *yrow = A.Y + row * A.ldy + cbase;
+            if (cbase + VN <= A.r) {
+#pragma unroll
+                for (int q = 0; q < VN; q += 4) {
+                    v4f y;
+                    if (MODE & M_FIRST) {
+                        y.x = a0 * own[q] + aj1 * nxt[q];
+                        y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
+                        y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
+                        y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
+                    } else {
+                        y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
+                        y.x = fmaf(aj1, nxt[q], y.x);
+                        y.y = fmaf(aj1, nxt[q + 1], y.y);
+                        y.z = fmaf(aj1, nxt[q + 2], y.z);
+                        y.w = fmaf(aj1, nxt[q + 3], y.w);
+                    }
+                    stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < VN; ++q) {
+                    if (cbase + q < A.r) {
+                        if (MODE & M_FIRST)
+                            yrow[q] = a0 * own[q] + aj1 * nxt[q];
+                        else
+                            yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
+                    }
+                }
+            }
+        }
+        if (MODE & M_PART) {
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                const double o = own[q], x = stv[q];
+                if (MODE & M_FIRST) p_own += o * o;
+                p_cross += x * o;
+                p_sq += x * x;
+            }
+        }
+    }
+    if (MODE & M_PART) {
+        __shared__ double lds[3 * NT / 64];
+        double v[3] = {p_own, p_cross, p_sq};
+        block_sum<3, NT>(v, lds);
+        if (threadIdx.x == 0) {
+            double *pp = A.partials + (int64_t)blockIdx.x * 3;
+            pp[0] = v[0];
+            pp[1] = v[1];
+            pp[2] = v[2];
+        }
+    }
+}
+
+// d_i = 4 s_i / lmax - 2 (float32), beta = -4 / lmax; flags a bad lmax
+__global__ void diag_kernel(int64_t n, const double *__restrict__ s, const double *__restrict__ lmax,
+                            float *__restrict__ diag, float *__restrict__ beta, uint32_t *flags, int clear_flags) {
+    const double L = lmax[0];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        beta[0] = (float)(-4.0 / L);
+        uint32_t f = clear_flags ? 0u : flags[0];
+        if (!(L > 0.0) || isinf(L)) f |= ASC_FLAG_NONFINITE;
+        flags[0] = f;
+    }
+    if (i < n) diag[i] = (float)(4.0 * s[i] / L - 2.0);
+}
+
+// panel[i][c] = R[i][c0 + c] for c0 + c < r, else 0
+template <typename TS>
+__global__ void pack_kernel(int64_t n, const TS *__restrict__ R, int64_t ldr, int64_t c0, int64_t r, int rs,
+                            TS *__restrict__ panel) {
+    const int64_t total = n * rs;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / rs;
+        const int64_t c = q - i * rs;
+        panel[q] = (c0 + c < r) ? R[i * ldr + c0 + c] : TS(0);
+    }
+}
+
+// Y = a_0 R (order 0 filter)
+template <typename TS>
+__global__ void scale_copy_kernel(int64_t n, int64_t r, const TS *__restrict__ R, int64_t ldr,
+                                  const double *__restrict__ coeffs, float *__restrict__ Y, int64_t ldy) {
+    const float a0 = (float)coeffs[0];
+    const int64_t total = n * r;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / r, c = q - i * r;
+        float x;
+        if constexpr (sizeof(TS) == 4) x = (float)R[i * ldr + c];
+        else x = __uint_as_float(((uint32_t)R[i * ldr + c]) << 16);
+        Y[i * ldy + c] = a0 * x;
+    }
+}
+
+// sums of [nparts][3] partials in block order; out[3]
+__global__ void sum_partials_kernel(int nparts, const double *__restrict__ part, int nsteps, int64_t step_stride,
+                                    double *__restrict__ out) {
+    // one block per step; out[step*3 + q]
+    __shared__ double lds[3 * NT / 64];
+    const int step = blockIdx.x;
+    if (step >= nsteps) return;
+    const double *p = part + step * step_stride;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        v[0] += p[b * 3 + 0];
+        v[1] += p[b * 3 + 1];
+        v[2] += p[b * 3 + 2];
+    }
+    block_sum<3, NT>(v, lds);
+    if (threadIdx.x == 0) {
+        out[step * 3 + 0] = v[0];
+        out[step * 3 + 1] = v[1];
+        out[step * 3 + 2] = v[2];
+    }
+}
+
+// growth / finiteness check of one slice: |T_p|^2 vs |T_0|^2
+__global__ void growth_check_kernel(const double *__restrict__ first, const double *__restrict__ last,
+                                    uint32_t *flags) {
+    if (threadIdx.x != 0) return;
+    const double n0 = first[0], np = last[2];
+    uint32_t f = flags[0];
+    if (!isfinite(n0) || !isfinite(np)) f |= ASC_FLAG_NONFINITE;
+    else if (np > 2.25 * n0 * (1.0 + 1e-6) + 1e-300) f |= ASC_FLAG_GROWTH;
+    flags[0] = f;
+}
+
+// mu_0..mu_p from per-slice per-step sums [nslices][steps][3]
+__global__ void moments_finalize_kernel(const double *__restrict__ sums, int nslices, int steps, int p,
+                                        double *__restrict__ mu, uint32_t *flags) {
+    if (threadIdx.x != 0) return;
+    auto tot = [&](int step, int q) {
+        double s = 0.0;
+        for (int sl = 0; sl < nslices; ++sl) s += sums[((int64_t)sl * steps + step) * 3 + q];
+        return s;
+    };
+    const double mu0 = tot(0, 0);
+    const double mu1 = tot(0, 1);
+    mu[0] = mu0;
+    bool bad = !isfinite(mu0);
+    for (int s = 0; s < steps; ++s) {
+        const int jo = 2 * s + 1, je = 2 * s + 2;
+        const double cross = tot(s, 1), sq = tot(s, 2);
+        if (jo <= p) mu[jo] = (s == 0) ? cross : 2.0 * cross - mu1;
+        if (je <= p) mu[je] = 2.0 * sq - mu0;
+        if (!isfinite(sq)) bad = true;
+        else if (sq > 2.25 * mu0 * (1.0 + 1e-6) + 1e-300) flags[0] |= ASC_FLAG_GROWTH;
+    }
+    if (bad) flags[0] |= ASC_FLAG_NONFINITE;
+}
+
+// ---------------------------------------------------------------------------
+// host-side planning and launch
+// ---------------------------------------------------------------------------
+struct Plan {
+    int lpr;     // lanes per row (2, 4, 8, 16)
+    int rs;      // panel width in elements = lpr * VN
+    int nslices;
+    unsigned var;
+};
+
+int vn_of(asc_dtype dt) { return dt == ASC_F32 ? 4 : 8; }
+
+int default_rs(int64_t r, asc_dtype dt) {
+    const int vn = vn_of(dt);
+    // smallest supported width covering r, capped at 32 float32 / 64 bfloat16 columns
+    const int cap = dt == ASC_F32 ? 32 : 64;
+    int rs = 2 * vn;
+    while (rs < r && rs < cap) rs *= 2;
+    return rs;
+}
+
+}  // namespace
+
+bool tuned(int64_t n, int64_t nnz, int64_t r, asc_dtype dt, TuneEntry *out) {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    for (auto &e : tune_table())
+        if (e.key == TuneKey{n, nnz, r, (int)dt}) {
+            if (out) *out = e;
+            return true;
+        }
+    return false;
+}
+
+namespace {
+
+bool valid_rs(int rs, asc_dtype dt) {
+    const int vn = dt == ASC_F32 ? 4 : 8;
+    return rs == 2 * vn || rs == 4 * vn || rs == 8 * vn || rs == 16 * vn;
+}
+
+Plan plan_for(int rs, unsigned var, int64_t r, asc_dtype dt) {
+    Plan P;
+    const int vn = vn_of(dt);
+    P.rs = rs;
+    P.lpr = rs / vn;
+    P.nslices = (int)((r + rs - 1) / rs);
+    P.var = var;
+    return P;
+}
+
+Plan make_plan(const asc_graph *g, int64_t r, asc_dtype dt) {
+    TuneEntry e;
+    if (tuned(g->n, g->nnz, r, dt, &e) && valid_rs(e.rs, dt)) return plan_for(e.rs, (unsigned)e.var, r, dt);
+    return plan_for(default_rs(r, dt), 0u, r, dt);
+}
+
+int grid_for(int64_t n, int lpr) {
+    const int64_t rows = (64 / lpr) * (NT / 64);
+    int64_t b = (n + rows - 1) / rows;
+    b = std::max<int64_t>(1, std::min<int64_t>(b, kMaxGrid));
+    return (int)b;
+}
+
+template <typename TS, int LPR, unsigned VAR>
+hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
+    switch (mode) {
+        case 0: cheb_step<TS, LPR, 0, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 1: cheb_step<TS, LPR, 1, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 2: cheb_step<TS, LPR, 2, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 3: cheb_step<TS, LPR, 3, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 4: cheb_step<TS, LPR, 4, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 5: cheb_step<TS, LPR, 5, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 6: cheb_step<TS, LPR, 6, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 7: cheb_step<TS, LPR, 7, VAR><<<grid, NT, 0, s>>>(A); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TS, int LPR>
+hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int grid, hipStream_t s) {
+    if (var & 1u) return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
+    return launch_step_v<TS, LPR, 0u>(mode, A, grid, s);
+}
+
+hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const StepArgs &A, int grid,
+                       hipStream_t s) {
+    if (dt == ASC_F32) {
+        switch (lpr) {
+            case 2: return launch_step_t<float, 2>(mode, var, A, grid, s);
+            case 4: return launch_step_t<float, 4>(mode, var, A, grid, s);
+            case 8: return launch_step_t<float, 8>(mode, var, A, grid, s);
+            case 16: return launch_step_t<float, 16>(mode, var, A, grid, s);
+        }
+    } else {
+        switch (lpr) {
+            case 2: return launch_step_t<uint16_t, 2>(mode, var, A, grid, s);
+            case 4: return launch_step_t<uint16_t, 4>(mode, var, A, grid, s);
+            case 8: return launch_step_t<uint16_t, 8>(mode, var, A, grid, s);
+            case 16: return launch_step_t<uint16_t, 16>(mode, var, A, grid, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t esize(asc_dtype dt) { return dt == ASC_F32 ? 4 : 2; }
+
+// workspace layout shared by the filter and the moment pass
+struct FilterWs {
+    WsHeader *hdr;
+    float *diag;
+    float *beta;
+    double *part;      // [steps_part][kMaxGrid][3]
+    double *sums;      // [nslices][steps][3]
+    double *first;     // [3]
+    void *panelA;
+    void *panelB;
+};
+
+size_t filter_ws_layout(int64_t n, int rs_max, int nslices, asc_dtype dt, int steps_part, int steps_sum,
+                        void *ws, FilterWs *out) {
+    Arena a(ws);
+    FilterWs f;
+    f.hdr = a.take<WsHeader>(1);
+    f.diag = a.take<float>(n);
+    f.beta = a.take<float>(64);
+    f.part = a.take<double>((size_t)steps_part * kMaxGrid * 3);
+    f.sums = a.take<double>((size_t)nslices * steps_sum * 3);
+    f.first = a.take<double>(64);
+    f.panelA = a.take<char>((size_t)n * rs_max * esize(dt));
+    f.panelB = a.take<char>((size_t)n * rs_max * esize(dt));
+    if (out) *out = f;
+    return a.size();
+}
+
+int rs_for_ws(int64_t r, asc_dtype dt) {
+    // the workspace must hold the widest panel any plan may pick
+    return std::max(default_rs(r, dt), dt == ASC_F32 ? 64 : 128);
+}
+
+asc_status check_common(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig, int64_t r,
+                        int64_t ldr, const char *who) {
+    ASC_TRY(check_graph_args(g, true, who));
+    if (!lmax || !aligned(lmax, 8)) return fail(ASC_ERR_INVALID, "%s: lmax NULL or misaligned", who);
+    if (p < 0 || p > 100000) return fail(ASC_ERR_INVALID, "%s: p=%d not in [0, 100000]", who, p);
+    ASC_TRY(check_block(R, sig, g->n, r, ldr, who, "R"));
+    return ASC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the filter, shared by asc_cheb_filter and the literal eigencount
+// ---------------------------------------------------------------------------
+asc_status run_filter(const asc_graph *g, const double *lmax, const double *coeffs, int p, const void *R,
+                      asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy, void *ckpt, int ckpt_stride,
+                      void *ws, bool clear_flags, hipStream_t s) {
+    const int64_t n = g->n;
+    FilterWs F;
+    const Plan P = make_plan(g, r, sig);
+    filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 2, 1, ws, &F);
+    uint32_t *flags = &F.hdr->flags;
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, flags,
+                                                           clear_flags ? 1 : 0);
+    ASC_LAUNCHED();
+    if (p == 0) {
+        const int64_t tot = n * r;
+        const int grid = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+        if (sig == ASC_F32)
+            scale_copy_kernel<float><<<grid, 256, 0, s>>>(n, r, (const float *)R, ldr, coeffs, Y, ldy);
+        else
+            scale_copy_kernel<uint16_t><<<grid, 256, 0, s>>>(n, r, (const uint16_t *)R, ldr, coeffs, Y, ldy);
+        ASC_LAUNCHED();
+        return ASC_OK;
+    }
+    (void)ckpt;
+    (void)ckpt_stride;
+    const int grid = grid_for(n, P.lpr);
+    const size_t panel_bytes = (size_t)n * P.rs * esize(sig);
+    (void)panel_bytes;
+    for (int sl = 0; sl < P.nslices; ++sl) {
+        const int64_t c0 = (int64_t)sl * P.rs;
+        {
+            const int64_t tot = n * P.rs;
+            const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+            if (sig == ASC_F32)
+                pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)F.panelA);
+            else
+                pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs,
+                                                         (uint16_t *)F.panelA);
+            ASC_LAUNCHED();
+        }
+        StepArgs A{};
+        A.n = n;
+        A.rp = g->row_ptr;
+        A.ci = g->col_idx;
+        A.w = g->w;
+        A.diag = F.diag;
+        A.beta = F.beta;
+        A.Y = Y;
+        A.ldy = ldy;
+        A.c0 = c0;
+        A.r = r;
+        A.coeffs = coeffs;
+        void *pa = F.panelA, *pb = F.panelB;  // pa holds T_j-1 .. ; cur alternates
+        // step 0: T_1 from T_0 (in A) into B
+        A.cur = pa;
+        A.prev = nullptr;
+        A.out = pb;
+        A.j = 0;
+        A.partials = F.part;  // partial slot 0: first step
+        hipError_t e = launch_step(sig, P.lpr, P.var, M_FIRST | M_YACC | M_PART, A, grid, s);
+        if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+        sum_partials_kernel<<<1, NT, 0, s>>>(grid, F.part, 1, 0, F.first);
+        ASC_LAUNCHED();
+        void *cur = pb, *prev = pa;
+        for (int j = 1; j < p; ++j) {
+            const bool last = (j == p - 1);
+            A.cur = cur;
+            A.prev = prev;
+            A.out = prev;  // T_{j+1} overwrites T_{j-1}
+            A.j = j;
+            A.partials = F.part + (int64_t)kMaxGrid * 3;
+            e = launch_step(sig, P.lpr, P.var, M_YACC | (last ? M_PART : 0u), A, grid, s);
+            if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+            std::swap(cur, prev);
+        }
+        const double *lastp = F.first;  // p == 1: the first step is the last
+        if (p > 1) {
+            sum_partials_kernel<<<1, NT, 0, s>>>(grid, F.part + (int64_t)kMaxGrid * 3, 1, 0, F.first + 3);
+            ASC_LAUNCHED();
+            lastp = F.first + 3;
+        }
+        growth_check_kernel<<<1, 64, 0, s>>>(F.first, lastp, flags);
+        ASC_LAUNCHED();
+    }
+    return ASC_OK;
+}
+
+asc_status run_moments(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig, int64_t r,
+                       int64_t ldr, double *mu, void *ws, hipStream_t s) {
+    const int64_t n = g->n;
+    const Plan P = make_plan(g, r, sig);
+    const int steps = std::max(1, (p + 1) / 2);
+    FilterWs F;
+    filter_ws_layout(n, rs_for_ws(r, sig), (int)((r + 2 * vn_of(sig) - 1) / (2 * vn_of(sig))), sig, steps, steps,
+                     ws, &F);
+    uint32_t *flags = &F.hdr->flags;
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, flags, 1);
+    ASC_LAUNCHED();
+    const int grid = grid_for(n, P.lpr);
+    for (int sl = 0; sl < P.nslices; ++sl) {
+        const int64_t c0 = (int64_t)sl * P.rs;
+        const int64_t tot = n * P.rs;
+        const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+        if (sig == ASC_F32)
+            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)F.panelA);
+        else
+            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)F.panelA);
+        ASC_LAUNCHED();
+        StepArgs A{};
+        A.n = n;
+        A.rp = g->row_ptr;
+        A.ci = g->col_idx;
+        A.w = g->w;
+        A.diag = F.diag;
+        A.beta = F.beta;
+        A.coeffs = nullptr;
+        void *cur = F.panelA, *prev = F.panelB;
+        for (int st = 0; st < steps; ++st) {
+            A.cur = cur;
+            A.prev = st == 0 ? nullptr : prev;
+            A.out = prev;
+            A.j = st;
+            A.partials = F.part + (int64_t)st * kMaxGrid * 3;
+            hipError_t e = launch_step(sig, P.lpr, P.var, (st == 0 ? M_FIRST : 0u) | M_PART, A, grid, s);
+            if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+            std::swap(cur, prev);
+        }
+        sum_partials_kernel<<<steps, NT, 0, s>>>(grid, F.part, steps, (int64_t)kMaxGrid * 3,
+                                                 F.sums + (int64_t)sl * steps * 3);
+        ASC_LAUNCHED();
+    }
+    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, P.nslices, steps, p, mu, flags);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+size_t moments_ws(int64_t n, int64_t r, asc_dtype sig, int p) {
+    const int steps = std::max(1, (p + 1) / 2);
+    const int nsl_max = (int)((r + 2 * vn_of(sig) - 1) / (2 * vn_of(sig)));
+    return filter_ws_layout(n, rs_for_ws(r, sig), nsl_max, sig, steps, steps, nullptr, nullptr);
+}
+
+size_t filter_ws(int64_t n, int64_t r, asc_dtype sig) {
+    return filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 2, 1, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// coefficients and the dichotomy (float64 on the device)
+// ---------------------------------------------------------------------------
+__device__ double cheb_coeff_dev(double lc, double L, int p, int j, int jackson) {
+    double xc = 2.0 * lc / L - 1.0;
+    xc = fmin(fmax(xc, -1.0), 1.0);
+    const double th = acos(xc);
+    double c = (j == 0) ? 1.0 - th / kPi : -2.0 * sin(j * th) / (j * kPi);
+    if (jackson) {
+        const double a = kPi / (p + 2);
+        const double g = ((p + 2 - j) * cos(j * a) + sin(j * a) / tan(a)) / (p + 2);
+        c *= g;
+    }
+    return c;
+}
+
+namespace {
+
+__global__ void coeffs_kernel(const double *__restrict__ lc, int n_cut, const double *__restrict__ lmax, int p,
+                              int jackson, double *__restrict__ out) {
+    const int64_t total = (int64_t)n_cut * (p + 1);
+    const double L = lmax[0];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int cut = (int)(q / (p + 1));
+        const int j = (int)(q - (int64_t)cut * (p + 1));
+        out[q] = cheb_coeff_dev(lc[cut], L, p, j, jackson);
+    }
+}
+
+// count(lc) = sum_j a_j(lc) mu_j, summed by the block in a fixed order
+__device__ double count_block(const double *mu, int p, double lc, double L, int jackson, double *lds) {
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j <= p; j += NT) v[0] += cheb_coeff_dev(lc, L, p, j, jackson) * mu[j];
+    block_sum<1, NT>(v, lds);
+    __shared__ double bc;
+    if (threadIdx.x == 0) bc = v[0];
+    __syncthreads();
+    const double r = bc;
+    __syncthreads();
+    return r;
+}
+
+__global__ void dichotomy_kernel(const double *__restrict__ mu, int p, const double *__restrict__ lmax, int k,
+                                 int steps, int jackson, double *__restrict__ lambda_k, double *__restrict__ traj) {
+    __shared__ double lds[NT / 64];
+    const double L = lmax[0];
+    double lo = 0.0, hi = L;
+    for (int s = 0; s < steps; ++s) {
+        const double mid = 0.5 * (lo + hi);
+        const double c = count_block(mu, p, mid, L, jackson, lds);
+        if (threadIdx.x == 0 && traj) {
+            traj[2 * s] = mid;
+            traj[2 * s + 1] = c;
+        }
+        if (c >= k - 0.5) hi = mid; else lo = mid;
+    }
+    if (threadIdx.x == 0) lambda_k[0] = hi;
+}
+
+// literal mode state: [lo, hi]
+__global__ void dich_lit_prepare(double *__restrict__ state, int s, const double *__restrict__ lmax, int p,
+                                 int jackson, double *__restrict__ coeffs, double *__restrict__ mid_out) {
+    (void)s;
+    const double L = lmax[0];
+    const double mid = 0.5 * (state[0] + state[1]);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= p; j += gridDim.x * blockDim.x)
+        coeffs[j] = cheb_coeff_dev(mid, L, p, j, jackson);
+    if (blockIdx.x == 0 && threadIdx.x == 0) mid_out[0] = mid;
+}
+
+__global__ void dich_lit_init(double *state, const double *lmax) {
+    if (threadIdx.x == 0) {
+        state[0] = 0.0;
+        state[1] = lmax[0];
+    }
+}
+
+// partial <R, Y> per block (float64)
+template <typename TS>
+__global__ void dot_RY_kernel(int64_t n, int64_t r, const TS *__restrict__ R, int64_t ldr, const float *__restrict__ Y,
+                              int64_t ldy, double *__restrict__ part) {
+    __shared__ double lds[NT / 64];
+    double v[1] = {0.0};
+    const int64_t total = n * r;
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < total; q += (int64_t)gridDim.x * NT) {
+        const int64_t i = q / r, c = q - i * r;
+        float x;
+        if constexpr (sizeof(TS) == 4) x = (float)R[i * ldr + c];
+        else x = __uint_as_float(((uint32_t)R[i * ldr + c]) << 16);
+        v[0] += (double)x * (double)Y[i * ldy + c];
+    }
+    block_sum<1, NT>(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ void dich_lit_update(double *__restrict__ state, int s, int k, int nparts, const double *__restrict__ part,
+                                const double *__restrict__ mid_in, double *__restrict__ traj,
+                                double *__restrict__ lambda_k, int last) {
+    if (threadIdx.x != 0) return;
+    double c = 0.0;
+    for (int b = 0; b < nparts; ++b) c += part[b];
+    const double mid = mid_in[0];
+    if (traj) {
+        traj[2 * s] = mid;
+        traj[2 * s + 1] = c;
+    }
+    if (c >= k - 0.5) state[1] = mid; else state[0] = mid;
+    if (last) lambda_k[0] = state[1];
+}
+
+__global__ void set_value_kernel(double *dst, const double *src) {
+    if (threadIdx.x == 0) dst[0] = src[1];
+}
+
+}  // namespace
+}  // namespace asc
+
+using namespace asc;
+
+extern "C" size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p) {
+    (void)p;
+    return filter_ws(n, r, sig);
+}
+
+extern "C" size_t asc_ckpt_bytes(int64_t n, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
+    (void)n; (void)r; (void)sig; (void)p; (void)ckpt_stride;
+    return 0;
+}
+
+extern "C" asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax, int p, int jackson,
+                                      double *coeffs, void *stream) {
+    const char *who = "asc_cheb_coeffs";
+    if (!lambda_c || !lmax || !coeffs) return fail(ASC_ERR_INVALID, "%s: NULL pointer", who);
+    if (!aligned(lambda_c, 8) || !aligned(lmax, 8) || !aligned(coeffs, 8)) return fail(ASC_ERR_INVALID, "%s: misaligned", who);
+    if (n_cut < 1 || p < 0 || p > 100000) return fail(ASC_ERR_INVALID, "%s: n_cut=%d p=%d", who, n_cut, p);
+    const int64_t total = (int64_t)n_cut * (p + 1);
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    coeffs_kernel<<<grid, 256, 0, as_stream(stream)>>>(lambda_c, n_cut, lmax, p, jackson, coeffs);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, const double *coeffs, int p,
+                                      const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
+                                      void *ckpt, int ckpt_stride, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_cheb_filter";
+    ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
+    if (!coeffs || !aligned(coeffs, 8)) return fail(ASC_ERR_INVALID, "%s: coeffs NULL or misaligned", who);
+    ASC_TRY(check_block(Y, ASC_F32, g->n, r, ldy, who, "Y"));
+    {
+        const char *rb = static_cast<const char *>(R);
+        const char *re = rb + (size_t)((g->n - 1) * ldr + r) * esize(sig);
+        const char *yb = reinterpret_cast<const char *>(Y);
+        const char *ye = yb + (size_t)((g->n - 1) * ldy + r) * 4;
+        if (rb < ye && yb < re) return fail(ASC_ERR_INVALID, "%s: Y overlaps R", who);
+    }
+    if (ckpt) return fail(ASC_ERR_INVALID, "%s: checkpoints are produced by asc_cheb_filter_ckpt", who);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_filter_workspace(g->n, r, sig, p), who));
+    return run_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, ckpt, ckpt_stride, ws, true, as_stream(stream));
+}
+
+extern "C" size_t asc_moments_workspace(int64_t n, int64_t r, asc_dtype sig, int p) { return moments_ws(n, r, sig, p); }
+
+extern "C" asc_status asc_cheb_moments(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig,
+                                       int64_t r, int64_t ldr, double *mu, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_cheb_moments";
+    ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
+    if (!mu || !aligned(mu, 8)) return fail(ASC_ERR_INVALID, "%s: mu NULL or misaligned", who);
+    ASC_TRY(check_ws(ws, ws_bytes, moments_ws(g->n, r, sig, p), who));
+    return run_moments(g, lmax, p, R, sig, r, ldr, mu, ws, as_stream(stream));
+}
+
+extern "C" asc_status asc_eigcount_dichotomy(const double *mu, int p, const double *lmax, int k, int steps,
+                                             int jackson, double *lambda_k, double *traj, void *stream) {
+    const char *who = "asc_eigcount_dichotomy";
+    if (!mu || !lmax || !lambda_k) return fail(ASC_ERR_INVALID, "%s: NULL pointer", who);
+    if (!aligned(mu, 8) || !aligned(lmax, 8) || !aligned(lambda_k, 8) || (traj && !aligned(traj, 8)))
+        return fail(ASC_ERR_INVALID, "%s: misaligned", who);
+    if (p < 0 || p > 100000 || k < 0 || steps < 0 || steps > 200)
+        return fail(ASC_ERR_INVALID, "%s: p=%d k=%d steps=%d", who, p, k, steps);
+    dichotomy_kernel<<<1, NT, 0, as_stream(stream)>>>(mu, p, lmax, k, steps, jackson, lambda_k, traj);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+extern "C" size_t asc_eigcount_workspace(int64_t n, int64_t r, asc_dtype sig, int p, int steps, int literal) {
+    (void)steps;
+    Arena a(nullptr);
+    if (literal) {
+        a.take<char>(filter_ws(n, r, sig));
+        a.take<double>(p + 1);         // coeffs
+        a.take<double>(64);            // state, mid
+        a.take<double>(kMaxGrid);      // dot partials
+        a.take<float>((size_t)n * ((r + 3) & ~int64_t(3)));  // Y
+    } else {
+        a.take<char>(moments_ws(n, r, sig, p));
+        a.take<double>(p + 1);  // mu
+    }
+    return a.size();
+}
+
+extern "C" asc_status asc_eigcount_lambda_k(const asc_graph *g, const double *lmax, int k, int p, int steps,
+                                            int literal, const void *R, asc_dtype sig, int64_t r, int64_t ldr,
+                                            double *lambda_k, double *traj, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_eigcount_lambda_k";
+    ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
+    if (!lambda_k || !aligned(lambda_k, 8) || (traj && !aligned(traj, 8)))
+        return fail(ASC_ERR_INVALID, "%s: lambda_k NULL or misaligned", who);
+    if (k < 0 || steps < 0 || steps > 200) return fail(ASC_ERR_INVALID, "%s: k=%d steps=%d", who, k, steps);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_eigcount_workspace(g->n, r, sig, p, steps, literal), who));
+    hipStream_t s = as_stream(stream);
+    Arena a(ws);
+    if (!literal) {
+        void *mws = a.take<char>(moments_ws(g->n, r, sig, p));
+        double *mu = a.take<double>(p + 1);
+        ASC_TRY(run_moments(g, lmax, p, R, sig, r, ldr, mu, mws, s));
+        dichotomy_kernel<<<1, NT, 0, s>>>(mu, p, lmax, k, steps, 1, lambda_k, traj);
+        ASC_LAUNCHED();
+        return ASC_OK;
+    }
+    void *fws = a.take<char>(filter_ws(g->n, r, sig));
+    double *coeffs = a.take<double>(p + 1);
+    double *state = a.take<double>(64);
+    double *part = a.take<double>(kMaxGrid);
+    const int64_t ldy = (r + 3) & ~int64_t(3);
+    float *Y = a.take<float>((size_t)g->n * ldy);
+    dich_lit_init<<<1, 64, 0, s>>>(state, lmax);
+    ASC_LAUNCHED();
+    if (steps == 0) {
+        set_value_kernel<<<1, 64, 0, s>>>(lambda_k, state);
+        ASC_LAUNCHED();
+        return ASC_OK;
+    }
+    const int64_t tot = g->n * r;
+    const int dg = (int)std::min<int64_t>((tot + NT - 1) / NT, kMaxGrid);
+    for (int st = 0; st < steps; ++st) {
+        dich_lit_prepare<<<(p + 256) / 256, 256, 0, s>>>(state, st, lmax, p, 1, coeffs, state + 2);
+        ASC_LAUNCHED();
+        ASC_TRY(run_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, nullptr, 0, fws, st == 0, s));
+        if (sig == ASC_F32)
+            dot_RY_kernel<float><<<dg, NT, 0, s>>>(g->n, r, (const float *)R, ldr, Y, ldy, part);
+        else
+            dot_RY_kernel<uint16_t><<<dg, NT, 0, s>>>(g->n, r, (const uint16_t *)R, ldr, Y, ldy, part);
+        ASC_LAUNCHED();
+        dich_lit_update<<<1, 64, 0, s>>>(state, st, k, dg, part, state + 2, traj, lambda_k, st == steps - 1);
+        ASC_LAUNCHED();
+    }
+    return ASC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times one recurrence step (all column slices) of every candidate
+// (slice width x kernel variant) on the caller's graph and signals, keeps the
+// fastest in the process-wide table.  Synchronises the stream.
+// ---------------------------------------------------------------------------
+namespace asc {
+namespace {
+__global__ void zero_f64(double *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+}  // namespace
+
+asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R, asc_dtype sig, int64_t r,
+                           int64_t ldr, float *Y, int64_t ldy, int probe_steps, void *ws, hipStream_t s,
+                           TuneEntry *best) {
+    const int64_t n = g->n;
+    FilterWs F;
+    filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 2, 1, ws, &F);
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, &F.hdr->flags, 1);
+    ASC_LAUNCHED();
+    zero_f64<<<1, 64, 0, s>>>(F.first, 64);  // coefficients read by the probe steps
+    ASC_LAUNCHED();
+    const int vn = vn_of(sig);
+    int64_t rcap = 2 * vn;
+    while (rcap < r) rcap *= 2;
+    hipEvent_t e0, e1;
+    ASC_HIP(hipEventCreate(&e0));
+    ASC_HIP(hipEventCreate(&e1));
+    TuneEntry bestE{};
+    bestE.ms = 1e30f;
+    asc_status st = ASC_OK;
+    for (int rs = 2 * vn; rs <= 16 * vn && rs <= rcap; rs *= 2) {
+        for (unsigned var = 0; var < 2; ++var) {
+            const Plan P = plan_for(rs, var, r, sig);
+            const int grid = grid_for(n, P.lpr);
+            const int64_t tot = n * P.rs;
+            const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+            for (void *panel : {F.panelA, F.panelB}) {
+                if (sig == ASC_F32)
+                    pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, 0, r, P.rs, (float *)panel);
+                else
+                    pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, 0, r, P.rs,
+                                                             (uint16_t *)panel);
+            }
+            StepArgs A{};
+            A.n = n;
+            A.rp = g->row_ptr;
+            A.ci = g->col_idx;
+            A.w = g->w;
+            A.diag = F.diag;
+            A.beta = F.beta;
+            A.Y = Y;
+            A.ldy = ldy;
+            A.r = r;
+            A.coeffs = F.first;
+            A.j = 0;
+            void *cur = F.panelA, *prev = F.panelB;
+            float ms = 0.f;
+            for (int it = -1; it < probe_steps; ++it) {
+                if (it == 0) hipEventRecord(e0, s);
+                for (int sl = 0; sl < P.nslices; ++sl) {
+                    A.c0 = (int64_t)sl * P.rs;
+                    A.cur = cur;
+                    A.prev = prev;
+                    A.out = prev;
+                    hipError_t e = launch_step(sig, P.lpr, P.var, M_YACC, A, grid, s);
+                    if (e != hipSuccess) {
+                        st = fail(ASC_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(e));
+                        break;
+                    }
+                }
+                std::swap(cur, prev);
+            }
+            if (st != ASC_OK) break;
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)std::max(1, probe_steps);
+            if (ms < bestE.ms) {
+                bestE.ms = ms;
+                bestE.rs = rs;
+                bestE.var = (int)var;
+            }
+        }
+        if (st != ASC_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != ASC_OK) return st;
+    bestE.key = TuneKey{n, g->nnz, r, (int)sig};
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        auto &t = tune_table();
+        bool found = false;
+        for (auto &e : t)
+            if (e.key == bestE.key) {
+                e = bestE;
+                found = true;
+            }
+        if (!found) t.push_back(bestE);
+    }
+    if (best) *best = bestE;
+    return ASC_OK;
+}
+}  // namespace asc
+
+extern "C" asc_status asc_tune_set(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int slice_cols, int variant) {
+    if (sig != ASC_F32 && sig != ASC_BF16) return fail(ASC_ERR_INVALID, "asc_tune_set: dtype");
+    if (slice_cols != 0 && !valid_rs(slice_cols, sig))
+        return fail(ASC_ERR_INVALID, "asc_tune_set: slice_cols=%d not supported for this dtype", slice_cols);
+    if (variant < 0 || variant > 1) return fail(ASC_ERR_INVALID, "asc_tune_set: variant=%d", variant);
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto &t = tune_table();
+    const TuneKey key{n, nnz, r, (int)sig};
+    for (size_t q = 0; q < t.size(); ++q)
+        if (t[q].key == key) {
+            if (slice_cols == 0) t.erase(t.begin() + q);
+            else t[q] = TuneEntry{key, slice_cols, variant, 0.f};
+            return ASC_OK;
+        }
+    if (slice_cols != 0) t.push_back(TuneEntry{key, slice_cols, variant, 0.f});
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_tune_get(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int *slice_cols, int *variant) {
+    if (!slice_cols || !variant) return fail(ASC_ERR_INVALID, "asc_tune_get: NULL output");
+    TuneEntry e;
+    if (tuned(n, nnz, r, sig, &e)) {
+        *slice_cols = e.rs;
+        *variant = e.var;
+    } else {
+        *slice_cols = default_rs(r, sig);
+        *variant = 0;
+    }
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_tune_save(const char *path) {
+    if (!path) return fail(ASC_ERR_INVALID, "asc_tune_save: NULL path");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(ASC_ERR_INVALID, "asc_tune_save: cannot open %s", path);
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    fprintf(f, "[\n");
+    const auto &t = tune_table();
+    for (size_t q = 0; q < t.size(); ++q) {
+        const auto &e = t[q];
+        fprintf(f, "{\"n\": %lld, \"nnz\": %lld, \"r\": %lld, \"dtype\": %d, \"slice_cols\": %d, \"variant\": %d, \"ms\": %.6f}%s\n",
+                (long long)e.key.n, (long long)e.key.nnz, (long long)e.key.r, e.key.dt, e.rs, e.var, (double)e.ms,
+                q + 1 < t.size() ? "," : "");
+    }
+    fprintf(f, "]\n");
+    fclose(f);
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_tune_load(const char *path) {
+    if (!path) return fail(ASC_ERR_INVALID, "asc_tune_load: NULL path");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(ASC_ERR_INVALID, "asc_tune_load: cannot open %s", path);
+    char line[512];
+    int loaded = 0;
+    while (fgets(line, sizeof line, f)) {
+        long long n, nnz, r;
+        int dt, rs, var;
+        double ms;
+        if (sscanf(line, " {\"n\": %lld, \"nnz\": %lld, \"r\": %lld, \"dtype\": %d, \"slice_cols\": %d, \"variant\": %d, \"ms\": %lf",
+                   &n, &nnz, &r, &dt, &rs, &var, &ms) == 7) {
+            if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && (var == 0 || var == 1)) {
+                asc_tune_set(n, nnz, r, (asc_dtype)dt, rs, var);
+                ++loaded;
+            }
+        }
+    }
+    fclose(f);
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_autotune_filter(const asc_graph *g, const double *lmax, const void *R, asc_dtype sig,
+                                          int64_t r, int64_t ldr, float *Y, int64_t ldy, int probe_steps, void *ws,
+                                          size_t ws_bytes, int *best_slice_cols, int *best_variant,
+                                          float *best_ms_per_step, void *stream) {
+    const char *who = "asc_autotune_filter";
+    ASC_TRY(check_common(g, lmax, 1, R, sig, r, ldr, who));
+    ASC_TRY(check_block(Y, ASC_F32, g->n, r, ldy, who, "Y"));
+    if (probe_steps < 1 || probe_steps > 1000) return fail(ASC_ERR_INVALID, "%s: probe_steps=%d", who, probe_steps);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_filter_workspace(g->n, r, sig, 1), who));
+    TuneEntry e;
+    ASC_TRY(autotune_filter(g, lmax, R, sig, r, ldr, Y, ldy, probe_steps, ws, as_stream(stream), &e));
+    if (best_slice_cols) *best_slice_cols = e.rs;
+    if (best_variant) *best_variant = e.var;
+    if (best_ms_per_step) *best_ms_per_step = e.ms;
+    return ASC_OK;
+}

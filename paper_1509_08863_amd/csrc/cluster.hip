@@ -1,0 +1,293 @@
+// Feature post-processing and clustering: row normalisation of the filtered
+// signals (footnote of Sec. 2.1) and k-means with the Euclidean distance
+// (Sec. 2.2 step 4; step 6 of the algorithm in Sec. 4.1).
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace asc {
+namespace {
+
+constexpr int NT = 256;
+
+// one wavefront per row: |y_i| accumulated in float64, y_i /= |y_i|
+__global__ __launch_bounds__(NT) void normalize_kernel(float *__restrict__ Y, int64_t n, int64_t r, int64_t ldy,
+                                                       float *__restrict__ norms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+    const int64_t stride = ((int64_t)gridDim.x * NT) >> 6;
+    for (int64_t i = row0; i < n; i += stride) {
+        float *y = Y + i * ldy;
+        double s = 0.0;
+        for (int64_t c = lane; c < r; c += 64) {
+            const double v = y[c];
+            s += v * v;
+        }
+        s = wave_sum(s);
+        const double nrm = sqrt(s);
+        if (nrm > 0.0) {
+            for (int64_t c = lane; c < r; c += 64) y[c] = (float)((double)y[c] / nrm);
+        }
+        if (norms && lane == 0) norms[i] = (float)nrm;
+    }
+}
+
+__global__ void init_rows_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
+                                 const int32_t *__restrict__ rows, int k, float *__restrict__ C) {
+    const int64_t total = (int64_t)k * r;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(q / r);
+        const int64_t col = q - (int64_t)c * r;
+        int64_t i = rows[c];
+        if (i < 0 || i >= n) i = 0;  // out-of-range rows read row 0 (validated on the host when possible)
+        C[q] = F[i * ldf + col];
+    }
+}
+
+// One wavefront per row, one lane per centroid: lane c accumulates
+// sum_col (F_i,col - C_c,col)^2 in float64 over the columns in order (no
+// fused multiply-add), then the wavefront takes the minimum with the lowest
+// index on ties.  The row index is wave-uniform, so F_i,col is a scalar load.
+// Centroids are staged transposed in LDS (Ct[col][c]) when they fit.
+__device__ __forceinline__ void better(double &d, int &c, double d2, int c2) {
+    if (d2 < d || (d2 == d && c2 < c)) {
+        d = d2;
+        c = c2;
+    }
+}
+
+__global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
+                                                    const float *__restrict__ Cg, int k, int use_lds,
+                                                    int32_t *__restrict__ labels, float *__restrict__ dist2) {
+#pragma clang fp contract(off)
+    extern __shared__ float Ct[];
+    const int kp = (k + 63) & ~63;
+    if (use_lds) {
+        for (int64_t q = threadIdx.x; q < (int64_t)kp * r; q += NT) {
+            const int64_t col = q / kp;
+            const int c = (int)(q - col * kp);
+            Ct[q] = c < k ? Cg[(int64_t)c * r + col] : 0.0f;
+        }
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
+    for (int64_t i = wave0; i < n; i += nwaves) {
+        const int64_t iu = __builtin_amdgcn_readfirstlane((int)i);
+        const float *f = F + iu * ldf;
+        double best = 0.0;
+        int bc = 0x7fffffff;
+        for (int g = 0; g < kp; g += 64) {
+            const int c = g + lane;
+            double d = 0.0;
+            if (use_lds) {
+                for (int64_t col = 0; col < r; ++col) {
+                    const double diff = (double)f[col] - (double)Ct[col * kp + c];
+                    const double sq = diff * diff;
+                    d = d + sq;
+                }
+            } else {
+                const int cc = c < k ? c : k - 1;
+                for (int64_t col = 0; col < r; ++col) {
+                    const double diff = (double)f[col] - (double)Cg[(int64_t)cc * r + col];
+                    const double sq = diff * diff;
+                    d = d + sq;
+                }
+            }
+            int ci = c;
+            if (c >= k) {
+                d = __builtin_huge_val();
+                ci = 0x7fffffff;
+            }
+            for (int off = 1; off < 64; off <<= 1) {
+                const double d2 = __shfl_xor(d, off, 64);
+                const int c2 = __shfl_xor(ci, off, 64);
+                better(d, ci, d2, c2);
+            }
+            if (g == 0) {
+                best = d;
+                bc = ci;
+            } else {
+                better(best, bc, d, ci);
+            }
+        }
+        if (lane == 0) {
+            labels[iu] = bc;
+            if (dist2) dist2[iu] = (float)best;
+        }
+    }
+}
+
+// per-block float64 sums of member rows, one thread per column, rows in
+// order (deterministic), partial [block][k][r] and counts [block][k]
+__global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
+                                      const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
+                                      double *__restrict__ part, int64_t *__restrict__ pcount) {
+    extern __shared__ double S[];  // k*r sums then k counts (as double)
+    const int64_t kr = (int64_t)k * r;
+    for (int64_t q = threadIdx.x; q < kr + k; q += blockDim.x) S[q] = 0.0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t i1 = min(n, i0 + rows_per_block);
+    constexpr int U = 8;
+    for (int64_t ib = i0; ib < i1; ib += U) {
+        int lab[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
+        for (int64_t col = threadIdx.x; col < r; col += blockDim.x) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (ib + u < i1) ? F[(ib + u) * ldf + col] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lab[u];
+                if (c >= 0 && c < k) S[(int64_t)c * r + col] += (double)v[u];
+            }
+        }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (lab[u] >= 0 && lab[u] < k) S[kr + lab[u]] += 1.0;
+        }
+    }
+    __syncthreads();
+    double *out = part + (int64_t)blockIdx.x * kr;
+    for (int64_t q = threadIdx.x; q < kr; q += blockDim.x) out[q] = S[q];
+    for (int q = threadIdx.x; q < k; q += blockDim.x) pcount[(int64_t)blockIdx.x * k + q] = (int64_t)S[kr + q];
+}
+
+// same, for k*r too large for LDS: sums kept in the partial array itself
+__global__ void update_partial_global_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
+                                             const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
+                                             double *__restrict__ part, int64_t *__restrict__ pcount) {
+    const int64_t kr = (int64_t)k * r;
+    double *S = part + (int64_t)blockIdx.x * kr;
+    for (int64_t q = threadIdx.x; q < kr; q += blockDim.x) S[q] = 0.0;
+    int64_t *cnt = pcount + (int64_t)blockIdx.x * k;
+    for (int q = threadIdx.x; q < k; q += blockDim.x) cnt[q] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t i1 = min(n, i0 + rows_per_block);
+    for (int64_t i = i0; i < i1; ++i) {
+        const int c = labels[i];
+        if (c < 0 || c >= k) continue;
+        for (int64_t col = threadIdx.x; col < r; col += blockDim.x) S[(int64_t)c * r + col] += (double)F[i * ldf + col];
+        if (threadIdx.x == 0) cnt[c] += 1;
+    }
+}
+
+// C[c][col] = (sum over blocks of the partial sums) / count; one wavefront
+// per (c, col): lanes take blocks b = lane, lane+64, ... in order, then the
+// fixed butterfly adds the 64 lane sums (deterministic).
+__global__ void update_final_kernel(int nblocks, int64_t r, int k, const double *__restrict__ part,
+                                    const int64_t *__restrict__ pcount, float *__restrict__ C,
+                                    int64_t *__restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const int64_t kr = (int64_t)k * r;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = w0; q < kr; q += nw) {
+        const int c = (int)(q / r);
+        double s = 0.0;
+        int64_t cnt = 0;
+        for (int b = lane; b < nblocks; b += 64) {
+            s += part[(int64_t)b * kr + q];
+            cnt += pcount[(int64_t)b * k + c];
+        }
+        s = wave_sum(s);
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+        if (lane == 0) {
+            if (cnt > 0) C[q] = (float)(s / (double)cnt);
+            if (counts && q - (int64_t)c * r == 0) counts[c] = cnt;
+        }
+    }
+}
+
+int update_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
+
+asc_status check_feat(const float *F, int64_t n, int64_t r, int64_t ldf, const char *who) {
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ASC_ERR_INVALID, "%s: n=%lld", who, (long long)n);
+    if (!F) return fail(ASC_ERR_INVALID, "%s: F is NULL", who);
+    if (r < 1 || r > 4096 || ldf < r) return fail(ASC_ERR_INVALID, "%s: r=%lld ldf=%lld", who, (long long)r, (long long)ldf);
+    if (!aligned(F, 4)) return fail(ASC_ERR_INVALID, "%s: F misaligned", who);
+    return ASC_OK;
+}
+
+}  // namespace
+}  // namespace asc
+
+using namespace asc;
+
+extern "C" asc_status asc_normalize_features(float *Y, int64_t n, int64_t r, int64_t ldy, float *norms, void *stream) {
+    const char *who = "asc_normalize_features";
+    if (!Y || n < 1 || n >= (int64_t(1) << 31) || r < 1 || r > 65536 || ldy < r || !aligned(Y, 4) ||
+        (norms && !aligned(norms, 4)))
+        return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
+    const int grid = (int)std::min<int64_t>((n * 64 + NT - 1) / NT, 16384);
+    normalize_kernel<<<grid, NT, 0, as_stream(stream)>>>(Y, n, r, ldy, norms);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_kmeans_init_rows(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *rows,
+                                           int k, float *C, void *stream) {
+    const char *who = "asc_kmeans_init_rows";
+    ASC_TRY(check_feat(F, n, r, ldf, who));
+    if (!rows || !C || k < 1 || k > 1024 || !aligned(rows, 4) || !aligned(C, 4))
+        return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
+    const int64_t total = (int64_t)k * r;
+    init_rows_kernel<<<(int)std::min<int64_t>((total + 255) / 256, 1024), 256, 0, as_stream(stream)>>>(F, n, r, ldf,
+                                                                                                        rows, k, C);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+extern "C" asc_status asc_kmeans_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k,
+                                        int32_t *labels, float *dist2, void *stream) {
+    const char *who = "asc_kmeans_assign";
+    ASC_TRY(check_feat(F, n, r, ldf, who));
+    if (!C || !labels || k < 1 || k > 1024 || !aligned(C, 4) || !aligned(labels, 4) || (dist2 && !aligned(dist2, 4)))
+        return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
+    const size_t cbytes = (size_t)((k + 63) & ~63) * r * sizeof(float);
+    const int use_lds = cbytes <= 64 * 1024;
+    const int grid = (int)std::min<int64_t>((n * 64 + NT - 1) / NT, 8192);
+    assign_kernel<<<grid, NT, use_lds ? cbytes : 0, as_stream(stream)>>>(F, n, r, ldf, C, k, use_lds, labels, dist2);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+extern "C" size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k) {
+    Arena a(nullptr);
+    const int nb = update_blocks(n);
+    a.take<double>((size_t)nb * k * r);
+    a.take<int64_t>((size_t)nb * k);
+    return a.size();
+}
+
+extern "C" asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels,
+                                        int k, float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_kmeans_update";
+    ASC_TRY(check_feat(F, n, r, ldf, who));
+    if (!labels || !C || k < 1 || k > 1024 || !aligned(labels, 4) || !aligned(C, 4) || (counts && !aligned(counts, 8)))
+        return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_kmeans_update_workspace(n, r, k), who));
+    Arena a(ws);
+    const int nb = update_blocks(n);
+    double *part = a.take<double>((size_t)nb * k * r);
+    int64_t *pcount = a.take<int64_t>((size_t)nb * k);
+    const int64_t rpb = (n + nb - 1) / nb;
+    hipStream_t s = as_stream(stream);
+    const size_t lds = ((size_t)k * r + k) * sizeof(double);
+    const int threads = (int)std::min<int64_t>(256, ((r + 63) / 64) * 64);
+    if (lds <= 64 * 1024)
+        update_partial_kernel<<<nb, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount);
+    else
+        update_partial_global_kernel<<<nb, threads, 0, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount);
+    ASC_LAUNCHED();
+    const int64_t kr = (int64_t)k * r;
+    update_final_kernel<<<(int)std::min<int64_t>((kr * 64 + 255) / 256, 4096), 256, 0, s>>>(nb, r, k, part, pcount, C,
+                                                                                           counts);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}

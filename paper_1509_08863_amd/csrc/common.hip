@@ -1,0 +1,76 @@
+// Error reporting, argument validation and the small utility entry points.
+#include "common.hpp"
+
+namespace asc {
+
+std::string &last_error_ref() {
+    static thread_local std::string s;
+    return s;
+}
+
+asc_status fail(asc_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    last_error_ref() = buf;
+    return st;
+}
+
+asc_status check_ws(const void *ws, size_t ws_bytes, size_t need, const char *who) {
+    if (need == 0) return ASC_OK;
+    if (ws == nullptr) return fail(ASC_ERR_WORKSPACE, "%s: workspace is NULL (need %zu bytes)", who, need);
+    if (!aligned(ws, 256)) return fail(ASC_ERR_WORKSPACE, "%s: workspace not 256-byte aligned", who);
+    if (ws_bytes < need)
+        return fail(ASC_ERR_WORKSPACE, "%s: workspace has %zu bytes, need %zu", who, ws_bytes, need);
+    return ASC_OK;
+}
+
+asc_status check_graph_args(const asc_graph *g, bool need_strength, const char *who) {
+    if (!g) return fail(ASC_ERR_INVALID, "%s: graph is NULL", who);
+    if (g->n < 1 || g->n >= (int64_t(1) << 31)) return fail(ASC_ERR_INVALID, "%s: n=%lld out of range", who, (long long)g->n);
+    if (g->nnz < 0 || g->nnz >= (int64_t(1) << 31))
+        return fail(ASC_ERR_INVALID, "%s: nnz=%lld out of range", who, (long long)g->nnz);
+    if (!g->row_ptr) return fail(ASC_ERR_INVALID, "%s: row_ptr is NULL", who);
+    if (g->nnz > 0 && !g->col_idx) return fail(ASC_ERR_INVALID, "%s: col_idx is NULL", who);
+    if (!aligned(g->row_ptr, 4) || (g->col_idx && !aligned(g->col_idx, 4)) || (g->w && !aligned(g->w, 4)))
+        return fail(ASC_ERR_INVALID, "%s: graph arrays must be 4-byte aligned", who);
+    if (need_strength && !g->strength)
+        return fail(ASC_ERR_INVALID, "%s: graph strength is NULL (call asc_graph_prepare)", who);
+    if (need_strength && !aligned(g->strength, 8)) return fail(ASC_ERR_INVALID, "%s: strength misaligned", who);
+    return ASC_OK;
+}
+
+asc_status check_block(const void *p, asc_dtype dt, int64_t n, int64_t r, int64_t ld, const char *who,
+                       const char *name) {
+    if (dt != ASC_F32 && dt != ASC_BF16) return fail(ASC_ERR_INVALID, "%s: unknown dtype %d", who, (int)dt);
+    if (!p) return fail(ASC_ERR_INVALID, "%s: %s is NULL", who, name);
+    if (r < 1 || r > 65536) return fail(ASC_ERR_INVALID, "%s: %s has r=%lld (1..65536)", who, name, (long long)r);
+    if (ld < r) return fail(ASC_ERR_INVALID, "%s: %s leading dimension %lld < r=%lld", who, name, (long long)ld, (long long)r);
+    const int64_t q = dt == ASC_F32 ? 4 : 8;
+    if (ld % q) return fail(ASC_ERR_INVALID, "%s: %s leading dimension must be a multiple of %lld", who, name, (long long)q);
+    if (!aligned(p, 16)) return fail(ASC_ERR_INVALID, "%s: %s must be 16-byte aligned", who, name);
+    (void)n;
+    return ASC_OK;
+}
+
+}  // namespace asc
+
+using namespace asc;
+
+extern "C" int asc_abi_version(void) { return ASC_ABI_VERSION; }
+
+extern "C" const char *asc_last_error(void) { return last_error_ref().c_str(); }
+
+extern "C" asc_status asc_read_flags(const void *ws, uint32_t *flags_host, void *stream) {
+    if (!ws || !aligned(ws, 256)) return fail(ASC_ERR_WORKSPACE, "asc_read_flags: bad workspace");
+    uint32_t f = 0;
+    ASC_HIP(hipMemcpyAsync(&f, ws, sizeof f, hipMemcpyDeviceToHost, as_stream(stream)));
+    ASC_HIP(hipStreamSynchronize(as_stream(stream)));
+    if (flags_host) *flags_host = f;
+    if (f & ASC_FLAG_NONFINITE) return fail(ASC_ERR_NONFINITE, "non-finite value in a filtered block");
+    if (f & ASC_FLAG_GROWTH)
+        return fail(ASC_ERR_LMAX_TOO_SMALL, "recurrence grew: |T_p R| > 1.5 |R|, lambda_max is below lambda_N");
+    return ASC_OK;
+}

@@ -1,0 +1,273 @@
+// Step 1 of the algorithm (Sec. 4.1): estimate of lambda_N, the largest
+// eigenvalue of L = S - W, by the Lanczos iteration in float64.
+//
+// Iteration j (v_j = u / beta_j, u the unnormalised Lanczos vector):
+//   w = L v_j - beta_j v_{j-1};  alpha_j = <w, v_j>;  u = w - alpha_j v_j;
+//   beta_{j+1} = |u|; stop when j + 1 == iters or beta_{j+1} <= 1e-12 max s.
+// The largest eigenvalue theta of the m x m tridiagonal (alpha, beta) is found
+// by Sturm-sequence bisection; lmax = min(1.01 theta, 2 max_i s_i).
+// Reductions are two-stage (per-block partials, then one block summing them
+// in index order), so the result is deterministic.
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace asc {
+namespace {
+
+constexpr int NT = 256;
+
+struct LzState {        // device-resident scalars
+    double smax;
+    int32_t stopped;
+    int32_t m;          // size of the tridiagonal once stopped
+    double pad[6];
+};
+
+constexpr int kMaxParts = 2048;
+
+// Sum of nparts per-block partials in a fixed order (strided per thread, then
+// the fixed-order block reduction); every block computes the same value.
+__device__ double sum_parts(const double *__restrict__ part, int nparts, double *lds) {
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) v[0] += part[b];
+    block_sum<1, NT>(v, lds);
+    __shared__ double bc;
+    if (threadIdx.x == 0) bc = v[0];
+    __syncthreads();
+    const double r = bc;
+    __syncthreads();
+    return r;
+}
+
+// u = v0, vprev = 0, partial |v0|^2 and max_i s_i
+__global__ void lz_init_kernel(int64_t n, const double *__restrict__ v0, const double *__restrict__ s,
+                               double *__restrict__ u, double *__restrict__ vprev, double *__restrict__ part,
+                               double *__restrict__ partmax) {
+    __shared__ double lds[NT / 64];
+    double acc[1] = {0.0};
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const double x = v0[i];
+        u[i] = x;
+        vprev[i] = 0.0;
+        acc[0] += x * x;
+        mx = fmax(mx, s[i]);
+    }
+    block_sum<1, NT>(acc, lds);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    __shared__ double lmx[NT / 64];
+    if ((threadIdx.x & 63) == 0) lmx[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < NT / 64; ++w) m = fmax(m, lmx[w]);
+        part[blockIdx.x] = acc[0];
+        partmax[blockIdx.x] = m;
+    }
+}
+
+// beta_0 = |v0|, smax; then v_0 = u / beta_0 (every block recomputes beta_0)
+__global__ void lz_start_kernel(int64_t n, int nparts, const double *__restrict__ part,
+                                const double *__restrict__ partmax, const double *__restrict__ u,
+                                double *__restrict__ vcur, double *__restrict__ beta, LzState *st) {
+    __shared__ double lds[NT / 64];
+    const double b = sqrt(sum_parts(part, nparts, lds));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double m = 0.0;
+        for (int q = 0; q < nparts; ++q) m = fmax(m, partmax[q]);
+        beta[0] = b;
+        st->smax = m;
+        st->stopped = (b == 0.0) ? 1 : 0;
+        st->m = 0;
+    }
+    if (b == 0.0) return;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) vcur[i] = u[i] / b;
+}
+
+// w = L v_j - beta_j v_{j-1}, partial <w, v_j>.  Eight lanes per row split
+// the row's entries; the lane partials are combined by a fixed butterfly.
+__global__ void lz_spmv_kernel(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const float *__restrict__ wgt, const double *__restrict__ s,
+                               const double *__restrict__ v, const double *__restrict__ vprev,
+                               double *__restrict__ wout, const double *__restrict__ beta, int j, const LzState *st,
+                               double *__restrict__ part) {
+    if (st->stopped) return;
+    __shared__ double lds[NT / 64];
+    constexpr int LPR = 8;
+    const double b = beta[j];
+    const int t = threadIdx.x & (LPR - 1);
+    double acc[1] = {0.0};
+    const int64_t rows_per_block = NT / LPR;
+    for (int64_t i0 = (int64_t)blockIdx.x * rows_per_block; i0 < n; i0 += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t i = i0 + threadIdx.x / LPR;
+        double sum = 0.0;
+        if (i < n) {
+            const int32_t e1 = rp[i + 1];
+            for (int32_t e = rp[i] + t; e < e1; e += LPR) sum += (wgt ? (double)wgt[e] : 1.0) * v[ci[e]];
+        }
+        sum += __shfl_xor(sum, 1, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        sum += __shfl_xor(sum, 4, 64);
+        if (i < n && t == 0) {
+            const double vi = v[i];
+            const double wi = (s[i] * vi - sum) - b * vprev[i];
+            wout[i] = wi;
+            acc[0] += wi * vi;
+        }
+    }
+    block_sum<1, NT>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// alpha_j = <w, v_j>; u = w - alpha_j v_j; partial |u|^2
+__global__ void lz_axpy_kernel(int64_t n, int nparts_in, const double *__restrict__ part_in,
+                               const double *__restrict__ wv, const double *__restrict__ vcur, double *__restrict__ u,
+                               double *__restrict__ alpha, int j, const LzState *st, double *__restrict__ part) {
+    if (st->stopped) return;
+    __shared__ double lds[NT / 64];
+    const double a = sum_parts(part_in, nparts_in, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] = a;
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const double x = wv[i] - a * vcur[i];
+        u[i] = x;
+        acc[0] += x * x;
+    }
+    block_sum<1, NT>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// beta_{j+1} = |u|; stop on the last iteration or on breakdown; else
+// v_{j+1} = u / beta_{j+1}
+__global__ void lz_scale_kernel(int64_t n, int nparts, const double *__restrict__ part, const double *__restrict__ u,
+                                double *__restrict__ vnext, double *__restrict__ beta, int j, int iters,
+                                LzState *st) {
+    if (st->stopped) return;
+    __shared__ double lds[NT / 64];
+    const double bn = sqrt(sum_parts(part, nparts, lds));
+    const bool stop = (j + 1 == iters) || bn <= 1e-12 * st->smax;
+    __syncthreads();  // every thread has read st->stopped / smax before block 0 updates them
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        beta[j + 1] = bn;
+        if (stop) {
+            st->stopped = 1;
+            st->m = j + 1;
+        }
+    }
+    if (stop) return;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) vnext[i] = u[i] / bn;
+}
+
+// number of eigenvalues of the tridiagonal strictly below x (Sturm sequence)
+__device__ int sturm_below(const double *a, const double *b, int m, double x) {
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < m; ++i) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = a[i] - x - b[i] * b[i] / qq;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// largest eigenvalue of T = tridiag(beta[1..m-1], alpha[0..m-1], beta[1..m-1])
+__global__ void lz_tridiag_kernel(const double *__restrict__ alpha, const double *__restrict__ beta,
+                                  const LzState *st, double *__restrict__ lmax) {
+    if (threadIdx.x != 0) return;
+    const int m = st->m;
+    const double smax = st->smax;
+    if (m <= 0) {  // zero start vector or no iteration: fall back to the Gershgorin bound
+        lmax[0] = 2.0 * smax;
+        return;
+    }
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? fabs(beta[i]) : 0.0) + (i + 1 < m ? fabs(beta[i + 1]) : 0.0);
+        lo = fmin(lo, alpha[i] - r);
+        hi = fmax(hi, alpha[i] + r);
+    }
+    // largest eigenvalue theta: sturm_below(x) == m  <=>  x > theta
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(alpha, beta, m, mid) == m) hi = mid; else lo = mid;
+    }
+    const double theta = hi;
+    lmax[0] = fmin(1.01 * theta, 2.0 * smax);
+}
+
+int nblocks_for(int64_t n) {
+    int64_t b = (n + NT - 1) / NT;
+    if (b > kMaxParts) b = kMaxParts;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+}  // namespace asc
+
+using namespace asc;
+
+extern "C" size_t asc_lmax_workspace(int64_t n, int iters) {
+    Arena a(nullptr);
+    a.take<WsHeader>(1);
+    a.take<LzState>(1);
+    for (int q = 0; q < 5; ++q) a.take<double>((size_t)n);  // u, vA, vB, w, (spare)
+    a.take<double>((size_t)iters + 2);                    // alpha
+    a.take<double>((size_t)iters + 2);                    // beta
+    a.take<double>(2048);                                 // partials
+    a.take<double>(2048);
+    return a.size();
+}
+
+extern "C" asc_status asc_lmax_estimate(const asc_graph *g, const double *v0, int iters, double *lmax,
+                                        double *lmax_host, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_lmax_estimate";
+    ASC_TRY(check_graph_args(g, true, who));
+    if (!v0 || !lmax || !aligned(v0, 8) || !aligned(lmax, 8)) return fail(ASC_ERR_INVALID, "%s: v0/lmax NULL or misaligned", who);
+    if (iters < 1 || iters > 4096) return fail(ASC_ERR_INVALID, "%s: iters=%d not in [1, 4096]", who, iters);
+    const int64_t n = g->n;
+    ASC_TRY(check_ws(ws, ws_bytes, asc_lmax_workspace(n, iters), who));
+    Arena a(ws);
+    a.take<WsHeader>(1);
+    LzState *st = a.take<LzState>(1);
+    double *u = a.take<double>(n);
+    double *vA = a.take<double>(n);
+    double *vB = a.take<double>(n);
+    double *wv = a.take<double>(n);
+    a.take<double>(n);
+    double *alpha = a.take<double>(iters + 2);
+    double *beta = a.take<double>(iters + 2);
+    double *part = a.take<double>(2048);
+    double *partmax = a.take<double>(2048);
+    hipStream_t s = as_stream(stream);
+    const int nb = nblocks_for(n);
+    const int nbs = (int)std::max<int64_t>(1, std::min<int64_t>((n + NT / 8 - 1) / (NT / 8), kMaxParts));
+    lz_init_kernel<<<nb, NT, 0, s>>>(n, v0, g->strength, u, vB, part, partmax);
+    ASC_LAUNCHED();
+    lz_start_kernel<<<nb, NT, 0, s>>>(n, nb, part, partmax, u, vA, beta, st);
+    ASC_LAUNCHED();
+    double *vcur = vA, *vprev = vB;
+    for (int j = 0; j < iters; ++j) {
+        lz_spmv_kernel<<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, g->strength, vcur, vprev, wv, beta, j, st,
+                                          part);
+        ASC_LAUNCHED();
+        lz_axpy_kernel<<<nb, NT, 0, s>>>(n, nbs, part, wv, vcur, u, alpha, j, st, partmax);
+        ASC_LAUNCHED();
+        // v_{j+1} overwrites v_{j-1}
+        lz_scale_kernel<<<nb, NT, 0, s>>>(n, nb, partmax, u, vprev, beta, j, iters, st);
+        ASC_LAUNCHED();
+        double *t = vprev;
+        vprev = vcur;
+        vcur = t;
+    }
+    lz_tridiag_kernel<<<1, 64, 0, s>>>(alpha, beta, st, lmax);
+    ASC_LAUNCHED();
+    if (lmax_host) {
+        ASC_HIP(hipMemcpyAsync(lmax_host, lmax, sizeof(double), hipMemcpyDeviceToHost, s));
+        ASC_HIP(hipStreamSynchronize(s));
+    }
+    return ASC_OK;
+}

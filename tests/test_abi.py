@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every symbol include/asc.h declares,
+and rejects bad arguments before any launch (host logic, no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1509_08863_amd import _abi
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "asc.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(asc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = _abi.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(L, nm), nm
+        assert nm in _abi.SIGNATURES, f"{nm} has no ctypes signature"
+    assert L.asc_abi_version() == 1
+
+
+def test_workspace_queries_are_host_only():
+    L = _abi.lib()
+    assert L.asc_filter_workspace(1000, 32, 0, 50) > 2 * 1000 * 32 * 4
+    assert L.asc_moments_workspace(100000, 64, 1, 100) > 0
+    assert L.asc_lmax_workspace(10, 5) > 0
+    assert L.asc_kmeans_update_workspace(1000, 8, 3) >= 1000 // 256 * 3 * 8 * 8
+
+
+def _g(n=10, nnz=0, strength=True):
+    fake = ctypes.c_void_p(0x1000)
+    return _abi.asc_graph(n, nnz, fake, fake, None, fake if strength else None)
+
+
+@pytest.mark.parametrize("case", ["p<0", "r=0", "ld<r", "ld%4", "misaligned", "no_strength", "null_Y", "ws_small"])
+def test_filter_rejects_before_launch(case):
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x10000)
+    g = _g(strength=case != "no_strength")
+    p, r, ldr, ldy, R, Y, wsb = 5, 8, 8, 8, fake, fake, 1 << 30
+    if case == "p<0":
+        p = -1
+    elif case == "r=0":
+        r = 0
+    elif case == "ld<r":
+        ldr = 4
+    elif case == "ld%4":
+        ldr = 10
+    elif case == "misaligned":
+        R = ctypes.c_void_p(0x10004)
+    elif case == "null_Y":
+        Y = None
+    elif case == "ws_small":
+        wsb = 16
+    st = L.asc_cheb_filter(ctypes.byref(g), fake, fake, p, R, 0, r, ldr, Y, ldy, None, 0, ctypes.c_void_p(0x100000),
+                           wsb, None)
+    assert st in (_abi.ASC_ERR_INVALID, _abi.ASC_ERR_WORKSPACE)
+    assert len(L.asc_last_error()) > 0
+
+
+def test_other_entry_points_reject():
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x10000)
+    assert L.asc_cheb_coeffs(fake, 0, fake, 3, 1, fake, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_lmax_estimate(ctypes.byref(_g()), fake, 0, fake, None, fake, 1 << 30, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeans_assign(fake, 10, 8, 8, fake, 0, fake, None, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_eigcount_dichotomy(fake, 5, fake, 3, 500, 1, fake, None, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_normalize_features(None, 10, 8, 8, None, None) == _abi.ASC_ERR_INVALID
+    g = _abi.asc_graph(0, 0, fake, fake, None, fake)
+    assert L.asc_graph_prepare(ctypes.byref(g), fake, 0, None, 0, None) == _abi.ASC_ERR_INVALID

@@ -1,0 +1,134 @@
+"""GPU parity of the moments, eigenvalue count and dichotomy (Sec. 3.2), row
+normalisation and k-means (Sec. 2.2 step 4, Sec. 4.1 step 6) against the
+FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+import paper_1509_08863_amd as asc
+
+from gpu_util import DEV, upload_graph, block_f32, block_bf16, scalar, host, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(g, p):
+    w = g.weights_or_ones().astype(np.float64)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w)
+    lmax = 1.01 * oracle.lambda_max_exact(L)
+    return L, lmax
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 5, 50, 51])
+@pytest.mark.parametrize("r", [4, 32, 33])
+def test_moments_match_oracle(p, r):
+    g = W.config_graph(1)
+    L, lmax = _setup(g, p)
+    G = upload_graph(g)
+    Rs, R64 = W.signals(g.n, r, 11)
+    mu = host(asc.cheb_moments(G, scalar(lmax), p, block_f32(Rs)))
+    ref = oracle.moments(L, lmax, p, R64)
+    # mu_0 = |R|^2 ~ n; float32 states give absolute errors ~1e-6 of mu_0
+    assert np.max(np.abs(mu - ref)) <= 1e-5 * ref[0]
+    # the count is a weighted sum of moments; compare it at a few cut-offs
+    for frac in (0.05, 0.17, 0.5):
+        c_gpu = float(np.dot(oracle.cheb_coeffs(frac * lmax, lmax, p), mu))
+        c_ref = oracle.eigcount_from_moments(ref, frac * lmax, lmax)
+        assert abs(c_gpu - c_ref) <= 1e-5 * ref[0] / np.sqrt(max(p, 1))
+
+
+def test_dichotomy_on_oracle_moments_is_exact():
+    # identical float64 moments in -> identical bisection decisions
+    g = W.config_graph(1)
+    L, lmax = _setup(g, 50)
+    R64 = W.signals(g.n, 32, 4)[1]
+    mu = oracle.moments(L, lmax, 50, R64)
+    est_ref, traj_ref = oracle.dichotomy(lambda lc: oracle.eigcount_from_moments(mu, lc, lmax), lmax, 10, 12)
+    lam, traj = asc.eigcount_dichotomy(to_dev(mu), scalar(lmax), 10, 12)
+    traj = host(traj)
+    np.testing.assert_array_equal(traj[:, 0], traj_ref[:, 0])
+    np.testing.assert_allclose(traj[:, 1], traj_ref[:, 1], rtol=1e-12, atol=1e-12)
+    assert host(lam)[0] == est_ref
+
+
+def _traj_agree(traj, traj_ref, k, tol):
+    """Trajectories agree until the first near tie |count - (k - 1/2)| <= tol."""
+    for s in range(len(traj_ref)):
+        if abs(traj_ref[s, 1] - (k - 0.5)) <= tol:
+            return True
+        assert traj[s, 0] == traj_ref[s, 0], s
+        assert abs(traj[s, 1] - traj_ref[s, 1]) <= tol, s
+    return True
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_lambda_k_matches_oracle(literal):
+    g = W.config_graph(1)
+    L, lmax = _setup(g, 50)
+    G = upload_graph(g)
+    Rs, R64 = W.signals(g.n, 32, 6)
+    est_ref, traj_ref = oracle.dichotomy_moments(L, lmax, 10, 50, 12, R64)
+    lam, traj = asc.eigcount_lambda_k(G, scalar(lmax), 10, 50, 12, block_f32(Rs), literal=literal)
+    _traj_agree(host(traj), traj_ref, 10, 1e-3)
+
+
+def test_large_gap_lambda_k():
+    k, m = 6, 16
+    g = W.cliques(k, m, bridges=True)
+    L, lmax = _setup(g, 120)
+    lam_all = np.linalg.eigvalsh(L.toarray())
+    G = upload_graph(g)
+    Rs, _ = W.signals(g.n, 64, 2)
+    lam, _ = asc.eigcount_lambda_k(G, scalar(lmax), k, 120, 14, block_f32(Rs))
+    assert lam_all[k - 1] < host(lam)[0] < lam_all[k]
+
+
+def test_normalize_matches_oracle():
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((3000, 50)).astype(np.float32)
+    Y[7] = 0
+    Yd = block_f32(Y, 52)
+    norms = asc.normalize_features(Yd)
+    F, nrm = oracle.normalize_rows(Y.astype(np.float64))
+    np.testing.assert_allclose(host(Yd), F, rtol=2e-7, atol=1e-30)
+    np.testing.assert_allclose(host(norms), nrm, rtol=1e-7)
+    assert np.all(host(Yd)[7] == 0)
+
+
+@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (1000, 96, 50), (333, 7, 3), (64, 130, 200)])
+def test_kmeans_assign_bit_exact(n, r, k):
+    rng = np.random.default_rng(n + k)
+    F = rng.standard_normal((n, r)).astype(np.float32)
+    C = rng.standard_normal((k, r)).astype(np.float32)
+    C[1] = C[0]  # an exact tie: lowest index wins
+    labels, dist2 = asc.kmeans_assign(block_f32(F), to_dev(C))
+    lab_ref, d_ref = oracle.kmeans_assign(F, C)
+    np.testing.assert_array_equal(host(labels), lab_ref)
+    np.testing.assert_array_equal(host(dist2), d_ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (20000, 96, 50), (100, 8, 7)])
+def test_kmeans_update_matches_oracle(n, r, k):
+    rng = np.random.default_rng(k)
+    F = rng.standard_normal((n, r)).astype(np.float32)
+    lab = rng.integers(0, k, n).astype(np.int32)
+    lab[lab == 2] = 0  # an empty cluster keeps its centroid
+    C0 = rng.standard_normal((k, r)).astype(np.float32)
+    Cd = to_dev(C0.copy())
+    counts = asc.kmeans_update(block_f32(F), to_dev(lab), Cd)
+    C_ref, cnt_ref = oracle.kmeans_update(F.astype(np.float64), lab, C0.astype(np.float64))
+    np.testing.assert_array_equal(host(counts), cnt_ref)
+    got = host(Cd)
+    ref32 = C_ref.astype(np.float32)
+    ulp = np.spacing(np.abs(ref32))
+    assert np.all(np.abs(got - ref32) <= ulp)
+    np.testing.assert_array_equal(got[2], C0[2])
+
+
+def test_kmeans_init_rows():
+    F = np.random.default_rng(1).standard_normal((100, 12)).astype(np.float32)
+    rows = np.array([3, 50, 99], dtype=np.int32)
+    C = asc.kmeans_init_rows(block_f32(F), to_dev(rows))
+    np.testing.assert_array_equal(host(C), F[rows])
