@@ -178,6 +178,44 @@ size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k);
 asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k,
                              float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- differentiation (extension beyond the paper) ----
+ * Conventions: lambda_max is a constant; every stored CSR entry e = (i,k) is
+ * its own parameter w_e, entering L as L_ik = -w_e and L_ii = sum_e w_e, so
+ * the gradient of an undirected edge is the sum of its two entries.
+ *
+ * Gaussian-kernel similarity (Sec. 2.2 step 1): w_e = exp(-d2_e / sigma^2),
+ * evaluated in float64 and stored in float32; sigma > 0.
+ * asc_gauss_weights_bwd: dsigma[1] = sum_e dW_e w_e 2 d2_e / sigma^3
+ * (float64, fixed-order reduction). */
+asc_status asc_gauss_weights(const float *d2, int64_t nnz, double sigma, float *w, void *stream);
+size_t asc_gauss_weights_bwd_workspace(int64_t nnz);
+asc_status asc_gauss_weights_bwd(const float *d2, const float *w, const float *dW, int64_t nnz, double sigma,
+                                 double *dsigma, void *ws, size_t ws_bytes, void *stream);
+
+/* Loss on the row-normalised features: loss[1] = sum_i |y_i/|y_i| - t_i|^2
+ * (float64) and G = dloss/dY = (g_i - f_i (f_i . g_i)) / |y_i| with
+ * f_i = y_i/|y_i|, g_i = 2 (f_i - t_i); rows with |y_i| = 0 get G_i = 0.
+ * Y, target, G: n x r float32 with leading dims ldy, ldt, ldg. */
+size_t asc_rownorm_loss_bwd_workspace(int64_t n);
+asc_status asc_rownorm_loss_bwd(const float *Y, int64_t ldy, const float *target, int64_t ldt, int64_t n, int64_t r,
+                                double *loss, float *G, int64_t ldg, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of asc_cheb_filter: given G = dloss/dY (n x r float32, ldg) and the
+ * checkpoints that asc_cheb_filter wrote with the same ckpt_stride (and the
+ * same R, coeffs, lmax and tuning), computes
+ *   dW[nnz]     = dloss/dw_e per stored entry (float32; NULL to skip),
+ *   dcoeffs[p+1] = <G, T_j R>_F (float64; NULL to skip)
+ * by the reverse recurrence A_p = a_p G, A_j = a_j G + 2 Lt A_{j+1} - A_{j+2},
+ * dw_(i,k) = (2/lmax)(M_ii - M_ik), M = A_1 T_0^T + sum_{j>=1} 2 A_{j+1} T_j^T.
+ * Recurrence states are recomputed segment by segment from the checkpoints.
+ * The sparsity pattern must be symmetric (entries without a stored transpose
+ * raise ASC_FLAG_BAD_GRAPH and keep dW = 0). */
+size_t asc_filter_bwd_workspace(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int p, int ckpt_stride);
+asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax, const double *coeffs, int p, const void *R,
+                               asc_dtype sig, int64_t r, int64_t ldr, const void *ckpt, int ckpt_stride,
+                               const float *G, int64_t ldg, float *dW, double *dcoeffs, void *ws, size_t ws_bytes,
+                               void *stream);
+
 /* Kernel configuration of the recurrence step, kept in a process-wide table
  * keyed by (n, nnz, r, sig); calls on a graph without an entry use the
  * default (slice width = the smallest of 8/16/32 float32 or 16/32/64 bfloat16

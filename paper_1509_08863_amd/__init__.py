@@ -19,7 +19,8 @@ from ._abi import AscError, ASC_F32, ASC_BF16  # noqa: F401
 __all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filter", "cheb_moments",
            "eigcount_dichotomy", "eigcount_lambda_k", "normalize_features", "kmeans_init_rows",
            "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
-           "tune_save", "tune_load", "autotune_filter"]
+           "tune_save", "tune_load", "autotune_filter", "cheb_filter_bwd", "gauss_weights", "gauss_weights_bwd",
+           "rownorm_loss_bwd"]
 
 
 def _stream():
@@ -105,7 +106,9 @@ def cheb_coeffs(lambda_c: torch.Tensor, lmax: torch.Tensor, p: int, jackson: boo
 
 
 def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, Y: torch.Tensor | None = None,
-                ws: torch.Tensor | None = None) -> torch.Tensor:
+                ws: torch.Tensor | None = None, ckpt_stride: int = 0):
+    """Y = sum_j a_j T_j(Lt) R.  With ckpt_stride >= 2 also returns the
+    checkpoint buffer that cheb_filter_bwd needs: (Y, ckpt)."""
     L = _abi.lib()
     coeffs = coeffs.reshape(-1)
     p = coeffs.numel() - 1
@@ -117,10 +120,57 @@ def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Ten
     need = L.asc_filter_workspace(n, r, dt, p)
     if ws is None or ws.numel() < need:
         ws = workspace(need, R.device)
+    ck = None
+    if ckpt_stride:
+        ck = workspace(L.asc_ckpt_bytes(n, r, dt, p, ckpt_stride), R.device)
     _abi.check(L.asc_cheb_filter(g.c(), _ptr(lmax), _ptr(coeffs), p, _ptr(R), dt, r, _ld(R), _ptr(Y), _ld(Y),
-                                 None, 0, _ptr(ws), ws.numel(), _stream()))
+                                 _ptr(ck), ckpt_stride, _ptr(ws), ws.numel(), _stream()))
     cheb_filter.last_ws = ws
-    return Y
+    return (Y, ck) if ckpt_stride else Y
+
+
+def cheb_filter_bwd(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, ckpt: torch.Tensor,
+                    ckpt_stride: int, G: torch.Tensor, want_dw: bool = True, want_dcoeffs: bool = True):
+    """(dW per stored entry float32 or None, dcoeffs float64 or None)."""
+    L = _abi.lib()
+    coeffs = coeffs.reshape(-1)
+    p = coeffs.numel() - 1
+    n, r = R.shape
+    dt = _dtype_code(R)
+    dW = torch.empty(g.nnz, dtype=torch.float32, device=R.device) if want_dw else None
+    dc = torch.empty(p + 1, dtype=torch.float64, device=R.device) if want_dcoeffs else None
+    ws = workspace(L.asc_filter_bwd_workspace(n, g.nnz, r, dt, p, ckpt_stride), R.device)
+    _abi.check(L.asc_cheb_filter_bwd(g.c(), _ptr(lmax), _ptr(coeffs), p, _ptr(R), dt, r, _ld(R), _ptr(ckpt),
+                                     ckpt_stride, _ptr(G), _ld(G), _ptr(dW), _ptr(dc), _ptr(ws), ws.numel(),
+                                     _stream()))
+    return dW, dc
+
+
+def gauss_weights(d2: torch.Tensor, sigma: float) -> torch.Tensor:
+    w = torch.empty_like(d2)
+    _abi.check(_abi.lib().asc_gauss_weights(_ptr(d2), d2.numel(), float(sigma), _ptr(w), _stream()))
+    return w
+
+
+def gauss_weights_bwd(d2: torch.Tensor, w: torch.Tensor, dW: torch.Tensor, sigma: float) -> torch.Tensor:
+    L = _abi.lib()
+    out = torch.empty(1, dtype=torch.float64, device=d2.device)
+    ws = workspace(L.asc_gauss_weights_bwd_workspace(d2.numel()), d2.device)
+    _abi.check(L.asc_gauss_weights_bwd(_ptr(d2), _ptr(w), _ptr(dW), d2.numel(), float(sigma), _ptr(out), _ptr(ws),
+                                       ws.numel(), _stream()))
+    return out
+
+
+def rownorm_loss_bwd(Y: torch.Tensor, target: torch.Tensor):
+    """(loss float64 [1], G = dloss/dY float32) for loss = sum_i |y_i/|y_i| - t_i|^2."""
+    L = _abi.lib()
+    n, r = Y.shape
+    loss = torch.empty(1, dtype=torch.float64, device=Y.device)
+    G = torch.empty(n, (r + 3) // 4 * 4, dtype=torch.float32, device=Y.device)[:, :r]
+    ws = workspace(L.asc_rownorm_loss_bwd_workspace(n), Y.device)
+    _abi.check(L.asc_rownorm_loss_bwd(_ptr(Y), _ld(Y), _ptr(target), _ld(target), n, r, _ptr(loss), _ptr(G), _ld(G),
+                                      _ptr(ws), ws.numel(), _stream()))
+    return loss, G
 
 
 def cheb_moments(g: Graph, lmax: torch.Tensor, p: int, R: torch.Tensor) -> torch.Tensor:

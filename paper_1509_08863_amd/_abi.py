@@ -64,6 +64,13 @@ SIGNATURES = {
     "asc_kmeans_update_workspace": (SZ, [I64, I64, I32]),
     "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
     "asc_read_flags": (I32, [P, ctypes.POINTER(ctypes.c_uint32), P]),
+    "asc_gauss_weights": (I32, [P, I64, D, P, P]),
+    "asc_gauss_weights_bwd_workspace": (SZ, [I64]),
+    "asc_gauss_weights_bwd": (I32, [P, P, P, I64, D, P, P, SZ, P]),
+    "asc_rownorm_loss_bwd_workspace": (SZ, [I64]),
+    "asc_rownorm_loss_bwd": (I32, [P, I64, P, I64, I64, I64, P, P, I64, P, SZ, P]),
+    "asc_filter_bwd_workspace": (SZ, [I64, I64, I64, I32, I32, I32]),
+    "asc_cheb_filter_bwd": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I32, P, I64, P, P, P, SZ, P]),
     "asc_tune_set": (I32, [I64, I64, I64, I32, I32, I32]),
     "asc_tune_get": (I32, [I64, I64, I64, I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "asc_tune_save": (I32, [ctypes.c_char_p]),

@@ -19,27 +19,14 @@
 // lane owning 16 bytes of the row: the gather of T_j[k] is one coalesced
 // 16*LPR-byte segment per neighbour.  Optional float64 partial sums per block
 // (|T_j|^2, <T_{j+1}, T_j>, |T_{j+1}|^2) feed the moments and the growth check.
-#include "common.hpp"
+#include "recurrence.hpp"
 
-#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
 
 namespace asc {
 
-// process-wide tuning table: kernel configuration per (n, nnz, r, dtype)
-struct TuneKey {
-    int64_t n, nnz, r;
-    int dt;
-    bool operator==(const TuneKey &o) const { return n == o.n && nnz == o.nnz && r == o.r && dt == o.dt; }
-};
-struct TuneEntry {
-    TuneKey key;
-    int rs;       // slice width (columns)
-    int var;      // kernel variant bits
-    float ms;     // measured time of one recurrence step over all columns
-};
 std::mutex &tune_mutex() {
     static std::mutex m;
     return m;
@@ -48,352 +35,6 @@ std::vector<TuneEntry> &tune_table() {
     static std::vector<TuneEntry> t;
     return t;
 }
-
-namespace {
-
-constexpr int NT = 256;          // threads per block (4 wavefronts)
-constexpr int kMaxGrid = 8192;   // cap of blocks per step launch (grid-stride beyond)
-constexpr unsigned M_FIRST = 1u;  // step 0: T_1 = Lt T_0 (there is no T_{-1})
-constexpr unsigned M_YACC = 2u;   // Y += a_{j+1} T_{j+1}; with M_FIRST: Y = a_0 T_0 + a_1 T_1
-constexpr unsigned M_PART = 4u;   // write float64 partial sums
-constexpr double kPi = 3.14159265358979323846;
-
-// ---------------------------------------------------------------------------
-// storage element types: float (4 per 16 B) and bfloat16 bits (8 per 16 B)
-// ---------------------------------------------------------------------------
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
-
-template <typename TS> struct St;
-template <> struct St<float> { static constexpr int VN = 4; typedef v4f raw; };
-template <> struct St<uint16_t> { static constexpr int VN = 8; typedef v4u raw; };
-
-// loads/stores with an optional non-temporal hint (streamed data that is not
-// re-read in this step: CSR arrays, T_{j-1}, Y)
-template <bool NTH, typename T>
-__device__ __forceinline__ T ldx(const T *p) {
-    if constexpr (NTH) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-template <bool NTH, typename T>
-__device__ __forceinline__ void stx(T *p, T v) {
-    if constexpr (NTH) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-template <bool NTH = false>
-__device__ __forceinline__ v4f ldraw(const float *p) { return ldx<NTH>(reinterpret_cast<const v4f *>(p)); }
-template <bool NTH = false>
-__device__ __forceinline__ v4u ldraw(const uint16_t *p) { return ldx<NTH>(reinterpret_cast<const v4u *>(p)); }
-
-__device__ __forceinline__ void unpack(const v4f &x, float (&v)[4]) {
-    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-}
-__device__ __forceinline__ void unpack(const v4u &x, float (&v)[8]) {
-    v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
-    v[4] = bf16_lo(x.z); v[5] = bf16_hi(x.z); v[6] = bf16_lo(x.w); v[7] = bf16_hi(x.w);
-}
-// acc += w * x (one fused multiply-add per element, in element order)
-__device__ __forceinline__ void fma_raw(float (&acc)[4], float w, const v4f &x) {
-    acc[0] = fmaf(w, x.x, acc[0]); acc[1] = fmaf(w, x.y, acc[1]);
-    acc[2] = fmaf(w, x.z, acc[2]); acc[3] = fmaf(w, x.w, acc[3]);
-}
-__device__ __forceinline__ void fma_raw(float (&acc)[8], float w, const v4u &x) {
-    acc[0] = fmaf(w, bf16_lo(x.x), acc[0]); acc[1] = fmaf(w, bf16_hi(x.x), acc[1]);
-    acc[2] = fmaf(w, bf16_lo(x.y), acc[2]); acc[3] = fmaf(w, bf16_hi(x.y), acc[3]);
-    acc[4] = fmaf(w, bf16_lo(x.z), acc[4]); acc[5] = fmaf(w, bf16_hi(x.z), acc[5]);
-    acc[6] = fmaf(w, bf16_lo(x.w), acc[6]); acc[7] = fmaf(w, bf16_hi(x.w), acc[7]);
-}
-// store v rounded to the storage type; `r` receives the stored values
-__device__ __forceinline__ void st16(float *p, const float (&v)[4], float (&r)[4]) {
-    v4f x = {v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<v4f *>(p) = x;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = v[q];
-}
-__device__ __forceinline__ void st16(uint16_t *p, const float (&v)[8], float (&r)[8]) {
-    v4u x;
-    x.x = pack_bf16x2(v[0], v[1]); x.y = pack_bf16x2(v[2], v[3]);
-    x.z = pack_bf16x2(v[4], v[5]); x.w = pack_bf16x2(v[6], v[7]);
-    *reinterpret_cast<v4u *>(p) = x;
-    unpack(x, r);
-}
-
-struct StepArgs {
-    int64_t n;
-    const int32_t *rp;
-    const int32_t *ci;
-    const float *w;        // nullptr: unit weights
-    const float *diag;     // d_i (float32)
-    const float *beta;     // beta[0] = -4/lmax
-    const void *cur;       // panel T_j
-    const void *prev;      // panel T_{j-1} (unused with M_FIRST)
-    void *out;             // panel T_{j+1} (may equal prev)
-    float *Y;              // caller block (slice columns c0..)
-    int64_t ldy, c0, r;
-    const double *coeffs;  // a_0..a_p
-    int j;                 // this step produces T_{j+1}
-    double *partials;      // [gridDim.x][3]
-};
-
-// Kernel variants (VAR bits): bit 0 = non-temporal hints on the streamed
-// arrays.  The neighbour loop gathers U rows per iteration and prefetches the
-// next U column indices / weights while the gathers are in flight.
-template <typename TS, int LPR, unsigned MODE, unsigned VAR>
-__global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
-    constexpr bool NTH = (VAR & 1u) != 0;
-    constexpr int VN = St<TS>::VN;
-    constexpr int RS = LPR * VN;
-    constexpr int RPW = 64 / LPR;
-    constexpr int ROWS = RPW * (NT / 64);
-    constexpr int U = 8;
-    typedef typename St<TS>::raw raw_t;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int t = lane % LPR;
-    const int sub = lane / LPR;
-    const TS *__restrict__ cur = static_cast<const TS *>(A.cur);
-    const TS *__restrict__ prv = static_cast<const TS *>(A.prev);
-    TS *__restrict__ out = static_cast<TS *>(A.out);
-    const float beta = A.beta[0];
-    const float aj1 = (MODE & M_YACC) ? (float)A.coeffs[A.j + 1] : 0.0f;
-    const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)A.coeffs[0] : 0.0f;
-    const bool weighted = A.w != nullptr;
-    double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
-    const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
-        if (row >= A.n) continue;
-        const int32_t e0 = ldx<NTH>(A.rp + row), e1 = ldx<NTH>(A.rp + row + 1);
-        float acc[VN];
-#pragma unroll
-        for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
-        const TS *base = cur + t * VN;
-        // padding slots gather the row itself with weight 0
-        int32_t kn[U];
-        float wn[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            kn[u] = (int32_t)row;
-            wn[u] = 0.0f;
-            if (e0 + u < e1) {
-                kn[u] = ldx<NTH>(A.ci + e0 + u);
-                wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
-            }
-        }
-        for (int32_t e = e0; e < e1; e += U) {
-            int32_t kc[U];
-            float wc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kc[u] = kn[u];
-                wc[u] = wn[u];
-            }
-            raw_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
-            const int32_t en = e + U;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kn[u] = (int32_t)row;
-                wn[u] = 0.0f;
-                if (en + u < e1) {
-                    kn[u] = ldx<NTH>(A.ci + en + u);
-                    wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
-        }
-        float own[VN], nxt[VN], stv[VN];
-        unpack(ldraw(cur + row * RS + t * VN), own);
-        const float d = ldx<NTH>(A.diag + row);
-        if (MODE & M_FIRST) {
-#pragma unroll
-            for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
-        } else {
-            float pv[VN];
-            unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
-#pragma unroll
-            for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
-        }
-        st16(out + row * RS + t * VN, nxt, stv);
-        if (MODE & M_YACC) {
-            const int64_t cbase = A.c0 + (int64_t)t * VN;
-            float *yrow = A.Y + row * A.ldy + cbase;
-            if (cbase + VN <= A.r) {
-#pragma unroll
-                for (int q = 0; q < VN; q += 4) {
-                    v4f y;
-                    if (MODE & M_FIRST) {
-                        y.x = a0 * own[q] + aj1 * nxt[q];
-                        y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
-                        y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
-                        y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
-                    } else {
-                        y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
-                        y.x = fmaf(aj1, nxt[q], y.x);
-                        y.y = fmaf(aj1, nxt[q + 1], y.y);
-                        y.z = fmaf(aj1, nxt[q + 2], y.z);
-                        y.w = fmaf(aj1, nxt[q + 3], y.w);
-                    }
-                    stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < VN; ++q) {
-                    if (cbase + q < A.r) {
-                        if (MODE & M_FIRST)
-                            yrow[q] = a0 * own[q] + aj1 * nxt[q];
-                        else
-                            yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
-                    }
-                }
-            }
-        }
-        if (MODE & M_PART) {
-#pragma unroll
-            for (int q = 0; q < VN; ++q) {
-                const double o = own[q], x = stv[q];
-                if (MODE & M_FIRST) p_own += o * o;
-                p_cross += x * o;
-                p_sq += x * x;
-            }
-        }
-    }
-    if (MODE & M_PART) {
-        __shared__ double lds[3 * NT / 64];
-        double v[3] = {p_own, p_cross, p_sq};
-        block_sum<3, NT>(v, lds);
-        if (threadIdx.x == 0) {
-            double *pp = A.partials + (int64_t)blockIdx.x * 3;
-            pp[0] = v[0];
-            pp[1] = v[1];
-            pp[2] = v[2];
-        }
-    }
-}
-
-// d_i = 4 s_i / lmax - 2 (float32), beta = -4 / lmax; flags a bad lmax
-__global__ void diag_kernel(int64_t n, const double *__restrict__ s, const double *__restrict__ lmax,
-                            float *__restrict__ diag, float *__restrict__ beta, uint32_t *flags, int clear_flags) {
-    const double L = lmax[0];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        beta[0] = (float)(-4.0 / L);
-        uint32_t f = clear_flags ? 0u : flags[0];
-        if (!(L > 0.0) || isinf(L)) f |= ASC_FLAG_NONFINITE;
-        flags[0] = f;
-    }
-    if (i < n) diag[i] = (float)(4.0 * s[i] / L - 2.0);
-}
-
-// panel[i][c] = R[i][c0 + c] for c0 + c < r, else 0
-template <typename TS>
-__global__ void pack_kernel(int64_t n, const TS *__restrict__ R, int64_t ldr, int64_t c0, int64_t r, int rs,
-                            TS *__restrict__ panel) {
-    const int64_t total = n * rs;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q / rs;
-        const int64_t c = q - i * rs;
-        panel[q] = (c0 + c < r) ? R[i * ldr + c0 + c] : TS(0);
-    }
-}
-
-// Y = a_0 R (order 0 filter)
-template <typename TS>
-__global__ void scale_copy_kernel(int64_t n, int64_t r, const TS *__restrict__ R, int64_t ldr,
-                                  const double *__restrict__ coeffs, float *__restrict__ Y, int64_t ldy) {
-    const float a0 = (float)coeffs[0];
-    const int64_t total = n * r;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q / r, c = q - i * r;
-        float x;
-        if constexpr (sizeof(TS) == 4) x = (float)R[i * ldr + c];
-        else x = __uint_as_float(((uint32_t)R[i * ldr + c]) << 16);
-        Y[i * ldy + c] = a0 * x;
-    }
-}
-
-// sums of [nparts][3] partials in block order; out[3]
-__global__ void sum_partials_kernel(int nparts, const double *__restrict__ part, int nsteps, int64_t step_stride,
-                                    double *__restrict__ out) {
-    // one block per step; out[step*3 + q]
-    __shared__ double lds[3 * NT / 64];
-    const int step = blockIdx.x;
-    if (step >= nsteps) return;
-    const double *p = part + step * step_stride;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nparts; b += NT) {
-        v[0] += p[b * 3 + 0];
-        v[1] += p[b * 3 + 1];
-        v[2] += p[b * 3 + 2];
-    }
-    block_sum<3, NT>(v, lds);
-    if (threadIdx.x == 0) {
-        out[step * 3 + 0] = v[0];
-        out[step * 3 + 1] = v[1];
-        out[step * 3 + 2] = v[2];
-    }
-}
-
-// growth / finiteness check of one slice: |T_p|^2 vs |T_0|^2
-__global__ void growth_check_kernel(const double *__restrict__ first, const double *__restrict__ last,
-                                    uint32_t *flags) {
-    if (threadIdx.x != 0) return;
-    const double n0 = first[0], np = last[2];
-    uint32_t f = flags[0];
-    if (!isfinite(n0) || !isfinite(np)) f |= ASC_FLAG_NONFINITE;
-    else if (np > 2.25 * n0 * (1.0 + 1e-6) + 1e-300) f |= ASC_FLAG_GROWTH;
-    flags[0] = f;
-}
-
-// mu_0..mu_p from per-slice per-step sums [nslices][steps][3]
-__global__ void moments_finalize_kernel(const double *__restrict__ sums, int nslices, int steps, int p,
-                                        double *__restrict__ mu, uint32_t *flags) {
-    if (threadIdx.x != 0) return;
-    auto tot = [&](int step, int q) {
-        double s = 0.0;
-        for (int sl = 0; sl < nslices; ++sl) s += sums[((int64_t)sl * steps + step) * 3 + q];
-        return s;
-    };
-    const double mu0 = tot(0, 0);
-    const double mu1 = tot(0, 1);
-    mu[0] = mu0;
-    bool bad = !isfinite(mu0);
-    for (int s = 0; s < steps; ++s) {
-        const int jo = 2 * s + 1, je = 2 * s + 2;
-        const double cross = tot(s, 1), sq = tot(s, 2);
-        if (jo <= p) mu[jo] = (s == 0) ? cross : 2.0 * cross - mu1;
-        if (je <= p) mu[je] = 2.0 * sq - mu0;
-        if (!isfinite(sq)) bad = true;
-        else if (sq > 2.25 * mu0 * (1.0 + 1e-6) + 1e-300) flags[0] |= ASC_FLAG_GROWTH;
-    }
-    if (bad) flags[0] |= ASC_FLAG_NONFINITE;
-}
-
-// ---------------------------------------------------------------------------
-// host-side planning and launch
-// ---------------------------------------------------------------------------
-struct Plan {
-    int lpr;     // lanes per row (2, 4, 8, 16)
-    int rs;      // panel width in elements = lpr * VN
-    int nslices;
-    unsigned var;
-};
-
-int vn_of(asc_dtype dt) { return dt == ASC_F32 ? 4 : 8; }
-
-int default_rs(int64_t r, asc_dtype dt) {
-    const int vn = vn_of(dt);
-    // smallest supported width covering r, capped at 32 float32 / 64 bfloat16 columns
-    const int cap = dt == ASC_F32 ? 32 : 64;
-    int rs = 2 * vn;
-    while (rs < r && rs < cap) rs *= 2;
-    return rs;
-}
-
-}  // namespace
 
 bool tuned(int64_t n, int64_t nnz, int64_t r, asc_dtype dt, TuneEntry *out) {
     std::lock_guard<std::mutex> lk(tune_mutex());
@@ -405,123 +46,7 @@ bool tuned(int64_t n, int64_t nnz, int64_t r, asc_dtype dt, TuneEntry *out) {
     return false;
 }
 
-namespace {
 
-bool valid_rs(int rs, asc_dtype dt) {
-    const int vn = dt == ASC_F32 ? 4 : 8;
-    return rs == 2 * vn || rs == 4 * vn || rs == 8 * vn || rs == 16 * vn;
-}
-
-Plan plan_for(int rs, unsigned var, int64_t r, asc_dtype dt) {
-    Plan P;
-    const int vn = vn_of(dt);
-    P.rs = rs;
-    P.lpr = rs / vn;
-    P.nslices = (int)((r + rs - 1) / rs);
-    P.var = var;
-    return P;
-}
-
-Plan make_plan(const asc_graph *g, int64_t r, asc_dtype dt) {
-    TuneEntry e;
-    if (tuned(g->n, g->nnz, r, dt, &e) && valid_rs(e.rs, dt)) return plan_for(e.rs, (unsigned)e.var, r, dt);
-    return plan_for(default_rs(r, dt), 0u, r, dt);
-}
-
-int grid_for(int64_t n, int lpr) {
-    const int64_t rows = (64 / lpr) * (NT / 64);
-    int64_t b = (n + rows - 1) / rows;
-    b = std::max<int64_t>(1, std::min<int64_t>(b, kMaxGrid));
-    return (int)b;
-}
-
-template <typename TS, int LPR, unsigned VAR>
-hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
-    switch (mode) {
-        case 0: cheb_step<TS, LPR, 0, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 1: cheb_step<TS, LPR, 1, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 2: cheb_step<TS, LPR, 2, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 3: cheb_step<TS, LPR, 3, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 4: cheb_step<TS, LPR, 4, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 5: cheb_step<TS, LPR, 5, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 6: cheb_step<TS, LPR, 6, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 7: cheb_step<TS, LPR, 7, VAR><<<grid, NT, 0, s>>>(A); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename TS, int LPR>
-hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int grid, hipStream_t s) {
-    if (var & 1u) return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
-    return launch_step_v<TS, LPR, 0u>(mode, A, grid, s);
-}
-
-hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const StepArgs &A, int grid,
-                       hipStream_t s) {
-    if (dt == ASC_F32) {
-        switch (lpr) {
-            case 2: return launch_step_t<float, 2>(mode, var, A, grid, s);
-            case 4: return launch_step_t<float, 4>(mode, var, A, grid, s);
-            case 8: return launch_step_t<float, 8>(mode, var, A, grid, s);
-            case 16: return launch_step_t<float, 16>(mode, var, A, grid, s);
-        }
-    } else {
-        switch (lpr) {
-            case 2: return launch_step_t<uint16_t, 2>(mode, var, A, grid, s);
-            case 4: return launch_step_t<uint16_t, 4>(mode, var, A, grid, s);
-            case 8: return launch_step_t<uint16_t, 8>(mode, var, A, grid, s);
-            case 16: return launch_step_t<uint16_t, 16>(mode, var, A, grid, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
-size_t esize(asc_dtype dt) { return dt == ASC_F32 ? 4 : 2; }
-
-// workspace layout shared by the filter and the moment pass
-struct FilterWs {
-    WsHeader *hdr;
-    float *diag;
-    float *beta;
-    double *part;      // [steps_part][kMaxGrid][3]
-    double *sums;      // [nslices][steps][3]
-    double *first;     // [3]
-    void *panelA;
-    void *panelB;
-};
-
-size_t filter_ws_layout(int64_t n, int rs_max, int nslices, asc_dtype dt, int steps_part, int steps_sum,
-                        void *ws, FilterWs *out) {
-    Arena a(ws);
-    FilterWs f;
-    f.hdr = a.take<WsHeader>(1);
-    f.diag = a.take<float>(n);
-    f.beta = a.take<float>(64);
-    f.part = a.take<double>((size_t)steps_part * kMaxGrid * 3);
-    f.sums = a.take<double>((size_t)nslices * steps_sum * 3);
-    f.first = a.take<double>(64);
-    f.panelA = a.take<char>((size_t)n * rs_max * esize(dt));
-    f.panelB = a.take<char>((size_t)n * rs_max * esize(dt));
-    if (out) *out = f;
-    return a.size();
-}
-
-int rs_for_ws(int64_t r, asc_dtype dt) {
-    // the workspace must hold the widest panel any plan may pick
-    return std::max(default_rs(r, dt), dt == ASC_F32 ? 64 : 128);
-}
-
-asc_status check_common(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig, int64_t r,
-                        int64_t ldr, const char *who) {
-    ASC_TRY(check_graph_args(g, true, who));
-    if (!lmax || !aligned(lmax, 8)) return fail(ASC_ERR_INVALID, "%s: lmax NULL or misaligned", who);
-    if (p < 0 || p > 100000) return fail(ASC_ERR_INVALID, "%s: p=%d not in [0, 100000]", who, p);
-    ASC_TRY(check_block(R, sig, g->n, r, ldr, who, "R"));
-    return ASC_OK;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // the filter, shared by asc_cheb_filter and the literal eigencount
@@ -547,9 +72,11 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         ASC_LAUNCHED();
         return ASC_OK;
     }
-    (void)ckpt;
-    (void)ckpt_stride;
     const int grid = grid_for(n, P.lpr);
+    const size_t ckb = ckpt ? ck_block_bytes(n, r, sig) : 0;
+    auto ck_block = [&](int seg, int which) -> void * {
+        return static_cast<char *>(ckpt) + ((size_t)seg * 2 + which) * ckb;
+    };
     const size_t panel_bytes = (size_t)n * P.rs * esize(sig);
     (void)panel_bytes;
     for (int sl = 0; sl < P.nslices; ++sl) {
@@ -583,6 +110,9 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         A.out = pb;
         A.j = 0;
         A.partials = F.part;  // partial slot 0: first step
+        A.ck_ld = ck_ld_of(r, sig);
+        A.ck_a = ckpt ? ck_block(0, 0) : nullptr;
+        A.ck_b = ckpt ? ck_block(0, 1) : nullptr;
         hipError_t e = launch_step(sig, P.lpr, P.var, M_FIRST | M_YACC | M_PART, A, grid, s);
         if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
         sum_partials_kernel<<<1, NT, 0, s>>>(grid, F.part, 1, 0, F.first);
@@ -595,6 +125,9 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
             A.out = prev;  // T_{j+1} overwrites T_{j-1}
             A.j = j;
             A.partials = F.part + (int64_t)kMaxGrid * 3;
+            const bool ck = ckpt && (j % ckpt_stride == 0);
+            A.ck_a = ck ? ck_block(j / ckpt_stride, 0) : nullptr;
+            A.ck_b = ck ? ck_block(j / ckpt_stride, 1) : nullptr;
             e = launch_step(sig, P.lpr, P.var, M_YACC | (last ? M_PART : 0u), A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
@@ -795,8 +328,8 @@ extern "C" size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int 
 }
 
 extern "C" size_t asc_ckpt_bytes(int64_t n, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
-    (void)n; (void)r; (void)sig; (void)p; (void)ckpt_stride;
-    return 0;
+    if (n < 1 || r < 1 || p < 0 || ckpt_stride < 2 || (sig != ASC_F32 && sig != ASC_BF16)) return 0;
+    return (size_t)nseg_of(p, ckpt_stride) * 2 * ck_block_bytes(n, r, sig);
 }
 
 extern "C" asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax, int p, int jackson,
@@ -826,7 +359,8 @@ extern "C" asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, co
         const char *ye = yb + (size_t)((g->n - 1) * ldy + r) * 4;
         if (rb < ye && yb < re) return fail(ASC_ERR_INVALID, "%s: Y overlaps R", who);
     }
-    if (ckpt) return fail(ASC_ERR_INVALID, "%s: checkpoints are produced by asc_cheb_filter_ckpt", who);
+    if (ckpt && (ckpt_stride < 2 || !aligned(ckpt, 256)))
+        return fail(ASC_ERR_INVALID, "%s: ckpt needs ckpt_stride >= 2 and 256-byte alignment", who);
     ASC_TRY(check_ws(ws, ws_bytes, asc_filter_workspace(g->n, r, sig, p), who));
     return run_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, ckpt, ckpt_stride, ws, true, as_stream(stream));
 }
