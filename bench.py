@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd timing")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tiling)")
+    ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
     return ap.parse_args()
 
 
@@ -82,6 +85,12 @@ def main():
     initd = torch.from_numpy(init).to(dev)
     Y = torch.empty(n, r, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+    tuned = {}
+    if not args.no_tune:
+        lm0 = asc.lmax_estimate(G, v0d, 60)
+        tuned["f32"] = asc.autotune_filter(G, lm0, R, 2)
+        if not args.no_bf16:
+            tuned["bf16"] = asc.autotune_filter(G, lm0, Rb, 2)
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     comp_names = ["prepare", "lmax", "lambda_k", "coeffs", "filter", "normalize", "kmeans"]
@@ -143,6 +152,31 @@ def main():
 
     ms_f32 = time_filter(R)
     ms_bf16 = None if args.no_bf16 else time_filter(Rb)
+
+    # forward + backward: filter with checkpoints, row-normalised loss against
+    # a fixed unit-row target, adjoint (edge-weight and coefficient gradients)
+    ms_fb = None
+    if not args.no_bwd:
+        from paper_1509_08863_amd.autograd import default_ckpt_stride
+        c = default_ckpt_stride(p)
+        target = torch.from_numpy(W.unit_rows(n, r, seeds["target"])).to(dev)
+        a = asc.cheb_coeffs(out[1], out[0], p)
+
+        def fwd_bwd():
+            Yf, ck = asc.cheb_filter(G, out[0], a, R, Y, ckpt_stride=c)
+            loss, Gr = asc.rownorm_loss_bwd(Yf, target)
+            return asc.cheb_filter_bwd(G, out[0], a, R, ck, c, Gr)
+
+        fwd_bwd()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        reps = 2
+        e0.record()
+        for _ in range(reps):
+            fwd_bwd()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fb = e0.elapsed_time(e1) / reps
     bs32 = b_step(n, nnz, r, 4)
     bs16 = b_step(n, nnz, r, 2)
     gbs32 = p * bs32 / (ms_f32 * 1e-3) / 1e9
@@ -199,7 +233,8 @@ def main():
         "config": {"workload": cfg["name"], "n": n, "nnz": nnz, "r": r, "p": p, "k": k,
                    "dichotomy_steps": steps_dich, "kmeans_iters": km_iters},
         "ms_per_filter_fwd": round(ms_f32, 4),
-        "ms_per_filter_fwd_bwd": None,
+        "ms_per_filter_fwd_bwd": None if ms_fb is None else round(ms_fb, 4),
+        "tuned": {k_: {"slice_cols": v[0], "variant": v[1], "ms_per_step": round(v[2], 4)} for k_, v in tuned.items()},
         "err_vs_fp64": err,
         "bf16": None if ms_bf16 is None else {"ms_per_filter_fwd": round(ms_bf16, 4), "gbs": round(gbs16, 2)},
         "components_ms": {k_: round(v, 4) for k_, v in comp.items()},

@@ -216,6 +216,31 @@ asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax, const dou
                                const float *G, int64_t ldg, float *dW, double *dcoeffs, void *ws, size_t ws_bytes,
                                void *stream);
 
+/* ---- batches of graphs (steps 2-5 of Sec. 4.1 for many graphs at once) ----
+ * The batch is one block-diagonal graph `g` (strength filled): graph q owns
+ * rows node_off_host[q] .. node_off_host[q+1]-1 and its columns stay in that
+ * range (node_off_host[0] = 0, node_off_host[n_graphs] = g->n; host arrays).
+ * For every graph q, asc_batch_run computes the Chebyshev moments of its rows
+ * of R (ceil(p/2) recurrence levels), runs the dichotomy for k_host[q] on
+ * [0, lmax[q]] for `steps` steps (lambda_k[q], traj[q][steps][2] = (mid,
+ * count)), then filters its rows of R at lambda_k[q] with the Jackson-damped
+ * order-p polynomial into Y.  All graphs advance in lockstep (one launch per
+ * recurrence level covers every graph); nothing returns to the host.
+ * tile_rows (0 = default) sets the rows of a work tile; tiles never straddle
+ * graphs.  With use_graph != 0 the whole sequence is captured into a HIP
+ * graph on the first call (and again whenever a pointer argument changes) and
+ * replayed as one launch.  The plan is host memory owned by the library
+ * (free with asc_batch_destroy); the device workspace comes from the caller
+ * (asc_batch_workspace bytes) and must not be shared by concurrent runs.
+ * 1 <= p <= 4000. */
+asc_status asc_batch_create(const asc_graph *g, int n_graphs, const int64_t *node_off_host, const int32_t *k_host,
+                            int64_t r, asc_dtype sig, int p, int steps, int tile_rows, void **plan);
+size_t asc_batch_workspace(const void *plan);
+asc_status asc_batch_info(const void *plan, int *slice_cols, int *tile_rows, int *ntiles);
+asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
+                         double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph, void *stream);
+asc_status asc_batch_destroy(void *plan);
+
 /* Kernel configuration of the recurrence step, kept in a process-wide table
  * keyed by (n, nnz, r, sig); calls on a graph without an entry use the
  * default (slice width = the smallest of 8/16/32 float32 or 16/32/64 bfloat16

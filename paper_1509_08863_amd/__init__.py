@@ -20,7 +20,7 @@ __all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filte
            "eigcount_dichotomy", "eigcount_lambda_k", "normalize_features", "kmeans_init_rows",
            "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
            "tune_save", "tune_load", "autotune_filter", "cheb_filter_bwd", "gauss_weights", "gauss_weights_bwd",
-           "rownorm_loss_bwd"]
+           "rownorm_loss_bwd", "Batch"]
 
 
 def _stream():
@@ -287,3 +287,43 @@ def autotune_filter(g: Graph, lmax: torch.Tensor, R: torch.Tensor, probe_steps: 
                                      _ptr(ws), ws.numel(), ctypes.byref(rs), ctypes.byref(var), ctypes.byref(ms),
                                      _stream()))
     return rs.value, var.value, ms.value
+
+
+class Batch:
+    """Batched lambda_k estimation + filtering of a block-diagonal graph
+    (asc_batch_*): graph q owns rows node_off[q]..node_off[q+1]-1."""
+
+    def __init__(self, g: Graph, node_off, k, r: int, dtype: torch.dtype, p: int, steps: int, tile_rows: int = 0):
+        import numpy as np
+        L = _abi.lib()
+        self._off = np.ascontiguousarray(node_off, dtype=np.int64)
+        self._k = np.ascontiguousarray(k, dtype=np.int32)
+        self.G = len(self._k)
+        self.g, self.r, self.p, self.steps = g, r, p, steps
+        self.dt = ASC_F32 if dtype == torch.float32 else ASC_BF16
+        h = ctypes.c_void_p(None)
+        _abi.check(L.asc_batch_create(g.c(), self.G, self._off.ctypes.data, self._k.ctypes.data, r, self.dt, p,
+                                      steps, tile_rows, ctypes.byref(h)))
+        self._h = h
+        self.ws = workspace(L.asc_batch_workspace(h), g.device)
+
+    def info(self):
+        a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _abi.check(_abi.lib().asc_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"slice_cols": a.value, "tile_rows": b.value, "ntiles": c.value}
+
+    def run(self, lmax: torch.Tensor, R: torch.Tensor, Y: torch.Tensor, lambda_k: torch.Tensor,
+            traj: torch.Tensor | None = None, use_graph: bool = True) -> None:
+        _abi.check(_abi.lib().asc_batch_run(self._h, _ptr(lmax), _ptr(R), _ld(R), _ptr(Y), _ld(Y), _ptr(lambda_k),
+                                            _ptr(traj), _ptr(self.ws), self.ws.numel(), int(use_graph), _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _abi.lib().asc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

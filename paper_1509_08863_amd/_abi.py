@@ -71,6 +71,12 @@ SIGNATURES = {
     "asc_rownorm_loss_bwd": (I32, [P, I64, P, I64, I64, I64, P, P, I64, P, SZ, P]),
     "asc_filter_bwd_workspace": (SZ, [I64, I64, I64, I32, I32, I32]),
     "asc_cheb_filter_bwd": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I32, P, I64, P, P, P, SZ, P]),
+    "asc_batch_create": (I32, [GP, I32, P, P, I64, I32, I32, I32, I32, ctypes.POINTER(ctypes.c_void_p)]),
+    "asc_batch_workspace": (SZ, [P]),
+    "asc_batch_info": (I32, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                             ctypes.POINTER(ctypes.c_int)]),
+    "asc_batch_run": (I32, [P, P, P, I64, P, I64, P, P, P, SZ, I32, P]),
+    "asc_batch_destroy": (I32, [P]),
     "asc_tune_set": (I32, [I64, I64, I64, I32, I32, I32]),
     "asc_tune_get": (I32, [I64, I64, I64, I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "asc_tune_save": (I32, [ctypes.c_char_p]),

@@ -118,130 +118,140 @@ struct StepArgs {
 // Kernel variants (VAR bits): bit 0 = non-temporal hints on the streamed
 // arrays.  The neighbour loop gathers U rows per iteration and prefetches the
 // next U column indices / weights while the gathers are in flight.
+// One row of a recurrence step (the LPR lanes of row group `t`): gather
+// sum_k w_ik T_j[k], form T_{j+1}[i] (or T_1 at the first step), store it (and
+// the checkpoints), update Y and the float64 partial sums.
 template <typename TS, int LPR, unsigned MODE, unsigned VAR>
-__global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
+__device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, const int t, const float beta,
+                                         const float aj1, const float a0, double &p_own, double &p_cross,
+                                         double &p_sq) {
     constexpr bool NTH = (VAR & 1u) != 0;
     constexpr int VN = St<TS>::VN;
     constexpr int RS = LPR * VN;
-    constexpr int RPW = 64 / LPR;
-    constexpr int ROWS = RPW * (NT / 64);
     constexpr int U = 8;
     typedef typename St<TS>::raw raw_t;
+    const TS *__restrict__ cur = static_cast<const TS *>(A.cur);
+    const TS *__restrict__ prv = static_cast<const TS *>(A.prev);
+    TS *__restrict__ out = static_cast<TS *>(A.out);
+    const bool weighted = A.w != nullptr;
+    const int32_t e0 = ldx<NTH>(A.rp + row), e1 = ldx<NTH>(A.rp + row + 1);
+    float acc[VN];
+#pragma unroll
+    for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
+    const TS *base = cur + t * VN;
+    // padding slots gather the row itself with weight 0
+    int32_t kn[U];
+    float wn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        kn[u] = (int32_t)row;
+        wn[u] = 0.0f;
+        if (e0 + u < e1) {
+            kn[u] = ldx<NTH>(A.ci + e0 + u);
+            wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
+        }
+    }
+    for (int32_t e = e0; e < e1; e += U) {
+        int32_t kc[U];
+        float wc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            kc[u] = kn[u];
+            wc[u] = wn[u];
+        }
+        raw_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+        const int32_t en = e + U;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            kn[u] = (int32_t)row;
+            wn[u] = 0.0f;
+            if (en + u < e1) {
+                kn[u] = ldx<NTH>(A.ci + en + u);
+                wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+    }
+    float own[VN], nxt[VN], stv[VN];
+    const raw_t own_raw = ldraw(cur + row * RS + t * VN);
+    unpack(own_raw, own);
+    if (A.ck_a) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_a) + row * A.ck_ld + A.c0 + t * VN) = own_raw;
+    const float d = ldx<NTH>(A.diag + row);
+    if (MODE & M_FIRST) {
+#pragma unroll
+        for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
+    } else {
+        float pv[VN];
+        unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
+#pragma unroll
+        for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
+    }
+    const raw_t nxt_raw = st16(out + row * RS + t * VN, nxt, stv);
+    if (A.ck_b) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_b) + row * A.ck_ld + A.c0 + t * VN) = nxt_raw;
+    if (MODE & M_YACC) {
+        const int64_t cbase = A.c0 + (int64_t)t * VN;
+        float *yrow = A.Y + row * A.ldy + cbase;
+        if (cbase + VN <= A.r) {
+#pragma unroll
+            for (int q = 0; q < VN; q += 4) {
+                v4f y;
+                if (MODE & M_FIRST) {
+                    y.x = a0 * own[q] + aj1 * nxt[q];
+                    y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
+                    y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
+                    y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
+                } else {
+                    y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
+                    y.x = fmaf(aj1, nxt[q], y.x);
+                    y.y = fmaf(aj1, nxt[q + 1], y.y);
+                    y.z = fmaf(aj1, nxt[q + 2], y.z);
+                    y.w = fmaf(aj1, nxt[q + 3], y.w);
+                }
+                stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                if (cbase + q < A.r) {
+                    if (MODE & M_FIRST)
+                        yrow[q] = a0 * own[q] + aj1 * nxt[q];
+                    else
+                        yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
+                }
+            }
+        }
+    }
+    if (MODE & M_PART) {
+#pragma unroll
+        for (int q = 0; q < VN; ++q) {
+            const double o = own[q], x = stv[q];
+            if (MODE & M_FIRST) p_own += o * o;
+            p_cross += x * o;
+            p_sq += x * x;
+        }
+    }
+}
+
+template <typename TS, int LPR, unsigned MODE, unsigned VAR>
+__global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
+    constexpr int RPW = 64 / LPR;
+    constexpr int ROWS = RPW * (NT / 64);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int t = lane % LPR;
     const int sub = lane / LPR;
-    const TS *__restrict__ cur = static_cast<const TS *>(A.cur);
-    const TS *__restrict__ prv = static_cast<const TS *>(A.prev);
-    TS *__restrict__ out = static_cast<TS *>(A.out);
     const float beta = A.beta[0];
     const float aj1 = (MODE & M_YACC) ? (float)A.coeffs[A.j + 1] : 0.0f;
     const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)A.coeffs[0] : 0.0f;
-    const bool weighted = A.w != nullptr;
     double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
     const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
         if (row >= A.n) continue;
-        const int32_t e0 = ldx<NTH>(A.rp + row), e1 = ldx<NTH>(A.rp + row + 1);
-        float acc[VN];
-#pragma unroll
-        for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
-        const TS *base = cur + t * VN;
-        // padding slots gather the row itself with weight 0
-        int32_t kn[U];
-        float wn[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            kn[u] = (int32_t)row;
-            wn[u] = 0.0f;
-            if (e0 + u < e1) {
-                kn[u] = ldx<NTH>(A.ci + e0 + u);
-                wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
-            }
-        }
-        for (int32_t e = e0; e < e1; e += U) {
-            int32_t kc[U];
-            float wc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kc[u] = kn[u];
-                wc[u] = wn[u];
-            }
-            raw_t v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
-            const int32_t en = e + U;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kn[u] = (int32_t)row;
-                wn[u] = 0.0f;
-                if (en + u < e1) {
-                    kn[u] = ldx<NTH>(A.ci + en + u);
-                    wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
-        }
-        float own[VN], nxt[VN], stv[VN];
-        const raw_t own_raw = ldraw(cur + row * RS + t * VN);
-        unpack(own_raw, own);
-        if (A.ck_a) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_a) + row * A.ck_ld + A.c0 + t * VN) = own_raw;
-        const float d = ldx<NTH>(A.diag + row);
-        if (MODE & M_FIRST) {
-#pragma unroll
-            for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
-        } else {
-            float pv[VN];
-            unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
-#pragma unroll
-            for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
-        }
-        const raw_t nxt_raw = st16(out + row * RS + t * VN, nxt, stv);
-        if (A.ck_b) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_b) + row * A.ck_ld + A.c0 + t * VN) = nxt_raw;
-        if (MODE & M_YACC) {
-            const int64_t cbase = A.c0 + (int64_t)t * VN;
-            float *yrow = A.Y + row * A.ldy + cbase;
-            if (cbase + VN <= A.r) {
-#pragma unroll
-                for (int q = 0; q < VN; q += 4) {
-                    v4f y;
-                    if (MODE & M_FIRST) {
-                        y.x = a0 * own[q] + aj1 * nxt[q];
-                        y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
-                        y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
-                        y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
-                    } else {
-                        y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
-                        y.x = fmaf(aj1, nxt[q], y.x);
-                        y.y = fmaf(aj1, nxt[q + 1], y.y);
-                        y.z = fmaf(aj1, nxt[q + 2], y.z);
-                        y.w = fmaf(aj1, nxt[q + 3], y.w);
-                    }
-                    stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < VN; ++q) {
-                    if (cbase + q < A.r) {
-                        if (MODE & M_FIRST)
-                            yrow[q] = a0 * own[q] + aj1 * nxt[q];
-                        else
-                            yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
-                    }
-                }
-            }
-        }
-        if (MODE & M_PART) {
-#pragma unroll
-            for (int q = 0; q < VN; ++q) {
-                const double o = own[q], x = stv[q];
-                if (MODE & M_FIRST) p_own += o * o;
-                p_cross += x * o;
-                p_sq += x * x;
-            }
-        }
+        step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
     }
     if (MODE & M_PART) {
         __shared__ double lds[3 * NT / 64];

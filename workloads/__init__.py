@@ -357,3 +357,25 @@ def random_weighted(n: int, p_edge: float, seed: int, isolated: int = 0) -> Grap
     u, v = iu[0][keep], iu[1][keep]
     w = rng.uniform(0.5, 2.0, size=u.shape[0])
     return from_edges(n, np.stack([u, v], 1), w)
+
+
+def concat_graphs(graphs):
+    """Block-diagonal concatenation: (Graph, node_off[int64 G+1]).  Columns of
+    graph q are shifted by node_off[q]; weights are kept (ones if absent)."""
+    off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for q, g in enumerate(graphs):
+        off[q + 1] = off[q] + g.n
+    nnz_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for q, g in enumerate(graphs):
+        nnz_off[q + 1] = nnz_off[q] + g.nnz
+    if nnz_off[-1] >= 2 ** 31:
+        raise ValueError("batch too large for int32 CSR")
+    rp = np.zeros(off[-1] + 1, dtype=np.int64)
+    ci = np.empty(nnz_off[-1], dtype=np.int64)
+    w = np.empty(nnz_off[-1], dtype=np.float32)
+    for q, g in enumerate(graphs):
+        rp[off[q] + 1: off[q + 1] + 1] = g.row_ptr[1:].astype(np.int64) + nnz_off[q]
+        ci[nnz_off[q]: nnz_off[q + 1]] = g.col_idx.astype(np.int64) + off[q]
+        w[nnz_off[q]: nnz_off[q + 1]] = g.weights_or_ones()
+    big = Graph(n=int(off[-1]), row_ptr=rp.astype(np.int32), col_idx=ci.astype(np.int32), w=w)
+    return big, off
