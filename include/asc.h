@@ -120,12 +120,17 @@ asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax
  * Y: n x r float32, leading dim ldy, must not overlap R.  coeffs[p+1] float64
  * (device), lmax[1] float64 (device).  Signal states are stored in `sig`,
  * arithmetic and the accumulation of Y are float32.
- * ckpt (may be NULL): receives the recurrence checkpoints used by
- * asc_cheb_filter_bwd, ckpt_stride >= 2; size from asc_ckpt_bytes.
+ * ckpt (may be NULL) receives what asc_cheb_filter_bwd needs, sized by
+ * asc_ckpt_bytes (256-byte aligned):
+ *   ckpt_stride >= 2: the pairs (T_sc R, T_sc+1 R), sc = 0, c, 2c, ... < p;
+ *   ckpt_stride == 1: every state T_0 R .. T_p R (the recurrence writes its
+ *     states into this store instead of reusing two buffers; no recompute in
+ *     the backward).  Its layout follows the tuning entry of (g, r, sig),
+ *     which must not change before the matching backward call.
  * The call also computes |T_0|_F and |T_p|_F and raises ASC_FLAG_GROWTH /
  * ASC_FLAG_NONFINITE in the workspace flags (asc_read_flags). */
 size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p);
-size_t asc_ckpt_bytes(int64_t n, int64_t r, asc_dtype sig, int p, int ckpt_stride);
+size_t asc_ckpt_bytes(const asc_graph *g, int64_t r, asc_dtype sig, int p, int ckpt_stride);
 asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, const double *coeffs, int p,
                            const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
                            void *ckpt, int ckpt_stride, void *ws, size_t ws_bytes, void *stream);
@@ -154,6 +159,21 @@ size_t asc_eigcount_workspace(int64_t n, int64_t r, asc_dtype sig, int p, int st
 asc_status asc_eigcount_lambda_k(const asc_graph *g, const double *lmax, int k, int p, int steps, int literal,
                                  const void *R, asc_dtype sig, int64_t r, int64_t ldr, double *lambda_k,
                                  double *traj, void *ws, size_t ws_bytes, void *stream);
+
+/* Steps 2-5 of Sec. 4.1 in ONE recurrence pass: runs T_0 R .. T_p R into the
+ * state store `states` (asc_ckpt_bytes(g, r, sig, p, 1) bytes), takes the
+ * Chebyshev moments from the first ceil(p/2) steps (as asc_cheb_moments),
+ * runs the dichotomy (as asc_eigcount_dichotomy; lambda_k[1], traj[steps][2]),
+ * computes the Jackson coefficients at lambda_k (coeffs_out[p+1], may be NULL)
+ * and forms Y = sum_j a_j T_j R from the stored states.  Equivalent to
+ * asc_eigcount_lambda_k + asc_cheb_coeffs + asc_cheb_filter without the
+ * second recurrence; `states` can feed asc_cheb_filter_bwd with
+ * ckpt_stride = 1 and these coefficients.  1 <= p. */
+size_t asc_lambda_k_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p);
+asc_status asc_lambda_k_filter(const asc_graph *g, const double *lmax, int k, int p, int steps, const void *R,
+                               asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy, double *lambda_k,
+                               double *traj, double *coeffs_out, void *states, void *ws, size_t ws_bytes,
+                               void *stream);
 
 /* Row normalisation of the features (footnote of Sec. 2.1): y_i <- y_i/|y_i|,
  * zero rows stay zero.  In place on Y (n x r float32, ldy); norms[n] (may be
@@ -202,12 +222,14 @@ asc_status asc_rownorm_loss_bwd(const float *Y, int64_t ldy, const float *target
 
 /* Adjoint of asc_cheb_filter: given G = dloss/dY (n x r float32, ldg) and the
  * checkpoints that asc_cheb_filter wrote with the same ckpt_stride (and the
- * same R, coeffs, lmax and tuning), computes
+ * same R, coeffs, lmax and tuning; ckpt_stride = 1: the full state store, also
+ * the one of asc_lambda_k_filter), computes
  *   dW[nnz]     = dloss/dw_e per stored entry (float32; NULL to skip),
  *   dcoeffs[p+1] = <G, T_j R>_F (float64; NULL to skip)
  * by the reverse recurrence A_p = a_p G, A_j = a_j G + 2 Lt A_{j+1} - A_{j+2},
  * dw_(i,k) = (2/lmax)(M_ii - M_ik), M = A_1 T_0^T + sum_{j>=1} 2 A_{j+1} T_j^T.
- * Recurrence states are recomputed segment by segment from the checkpoints.
+ * Recurrence states are recomputed segment by segment from the checkpoints
+ * (read directly from the store when ckpt_stride == 1).
  * The sparsity pattern must be symmetric (entries without a stored transpose
  * raise ASC_FLAG_BAD_GRAPH and keep dW = 0). */
 size_t asc_filter_bwd_workspace(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int p, int ckpt_stride);
@@ -263,6 +285,11 @@ asc_status asc_tune_load(const char *path);
 asc_status asc_autotune_filter(const asc_graph *g, const double *lmax, const void *R, asc_dtype sig, int64_t r,
                                int64_t ldr, float *Y, int64_t ldy, int probe_steps, void *ws, size_t ws_bytes,
                                int *best_slice_cols, int *best_variant, float *best_ms_per_step, void *stream);
+
+/* Plain device-to-device streaming copy of `bytes` (multiple of 16, 16-byte
+ * aligned pointers): the reference kernel for measured copy bandwidth and for
+ * calibrating memory counters. */
+asc_status asc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Health flags raised by the last filter / moment pass that used ws.
  * Synchronises the stream; flags_host gets ASC_FLAG_* bits.  Returns

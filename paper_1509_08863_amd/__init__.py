@@ -20,7 +20,8 @@ __all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filte
            "eigcount_dichotomy", "eigcount_lambda_k", "normalize_features", "kmeans_init_rows",
            "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
            "tune_save", "tune_load", "autotune_filter", "cheb_filter_bwd", "gauss_weights", "gauss_weights_bwd",
-           "rownorm_loss_bwd", "Batch"]
+           "rownorm_loss_bwd", "Batch", "stream_copy",
+           "lambda_k_filter"]
 
 
 def _stream():
@@ -106,7 +107,7 @@ def cheb_coeffs(lambda_c: torch.Tensor, lmax: torch.Tensor, p: int, jackson: boo
 
 
 def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, Y: torch.Tensor | None = None,
-                ws: torch.Tensor | None = None, ckpt_stride: int = 0):
+                ws: torch.Tensor | None = None, ckpt_stride: int = 0, ckpt: torch.Tensor | None = None):
     """Y = sum_j a_j T_j(Lt) R.  With ckpt_stride >= 2 also returns the
     checkpoint buffer that cheb_filter_bwd needs: (Y, ckpt)."""
     L = _abi.lib()
@@ -122,7 +123,8 @@ def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Ten
         ws = workspace(need, R.device)
     ck = None
     if ckpt_stride:
-        ck = workspace(L.asc_ckpt_bytes(n, r, dt, p, ckpt_stride), R.device)
+        need_ck = L.asc_ckpt_bytes(g.c(), r, dt, p, ckpt_stride)
+        ck = ckpt if (ckpt is not None and ckpt.numel() >= need_ck) else workspace(need_ck, R.device)
     _abi.check(L.asc_cheb_filter(g.c(), _ptr(lmax), _ptr(coeffs), p, _ptr(R), dt, r, _ld(R), _ptr(Y), _ld(Y),
                                  _ptr(ck), ckpt_stride, _ptr(ws), ws.numel(), _stream()))
     cheb_filter.last_ws = ws
@@ -205,6 +207,28 @@ def eigcount_lambda_k(g: Graph, lmax: torch.Tensor, k: int, p: int, steps: int, 
                                        _ptr(lam), _ptr(traj), _ptr(ws), ws.numel(), _stream()))
     eigcount_lambda_k.last_ws = ws
     return lam, traj[:steps]
+
+
+def lambda_k_filter(g: Graph, lmax: torch.Tensor, k: int, p: int, steps: int, R: torch.Tensor,
+                    Y: torch.Tensor | None = None, states: torch.Tensor | None = None):
+    """One recurrence pass: (Y, lambda_k, traj, coeffs, states); `states`
+    (all T_j R) can be passed to cheb_filter_bwd with ckpt_stride=1."""
+    L = _abi.lib()
+    n, r = R.shape
+    dt = _dtype_code(R)
+    if Y is None:
+        Y = torch.empty(n, (r + 3) // 4 * 4, dtype=torch.float32, device=R.device)[:, :r]
+    need = L.asc_ckpt_bytes(g.c(), r, dt, p, 1)
+    if states is None or states.numel() < need:
+        states = workspace(need, R.device)
+    lam = torch.empty(1, dtype=torch.float64, device=R.device)
+    traj = torch.empty(max(steps, 1), 2, dtype=torch.float64, device=R.device)
+    co = torch.empty(p + 1, dtype=torch.float64, device=R.device)
+    ws = workspace(L.asc_lambda_k_filter_workspace(n, r, dt, p), R.device)
+    _abi.check(L.asc_lambda_k_filter(g.c(), _ptr(lmax), k, p, steps, _ptr(R), dt, r, _ld(R), _ptr(Y), _ld(Y),
+                                     _ptr(lam), _ptr(traj), _ptr(co), _ptr(states), _ptr(ws), ws.numel(), _stream()))
+    lambda_k_filter.last_ws = ws
+    return Y, lam, traj[:steps], co, states
 
 
 def normalize_features(Y: torch.Tensor, want_norms: bool = True):
@@ -327,3 +351,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """dst <- src (same byte size), plain 16-byte streaming copy kernel."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    _abi.check(_abi.lib().asc_stream_copy(_ptr(src), _ptr(dst), nb, _stream()))

@@ -51,7 +51,9 @@ SIGNATURES = {
     "asc_lmax_estimate": (I32, [GP, P, I32, P, P, P, SZ, P]),
     "asc_cheb_coeffs": (I32, [P, I32, P, I32, I32, P, P]),
     "asc_filter_workspace": (SZ, [I64, I64, I32, I32]),
-    "asc_ckpt_bytes": (SZ, [I64, I64, I32, I32, I32]),
+    "asc_ckpt_bytes": (SZ, [GP, I64, I32, I32, I32]),
+    "asc_lambda_k_filter_workspace": (SZ, [I64, I64, I32, I32]),
+    "asc_lambda_k_filter": (I32, [GP, P, I32, I32, I32, P, I32, I64, I64, P, I64, P, P, P, P, P, SZ, P]),
     "asc_cheb_filter": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I64, P, I32, P, SZ, P]),
     "asc_moments_workspace": (SZ, [I64, I64, I32, I32]),
     "asc_cheb_moments": (I32, [GP, P, I32, P, I32, I64, I64, P, P, SZ, P]),
@@ -63,6 +65,7 @@ SIGNATURES = {
     "asc_kmeans_assign": (I32, [P, I64, I64, I64, P, I32, P, P, P]),
     "asc_kmeans_update_workspace": (SZ, [I64, I64, I32]),
     "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
+    "asc_stream_copy": (I32, [P, P, SZ, P]),
     "asc_read_flags": (I32, [P, ctypes.POINTER(ctypes.c_uint32), P]),
     "asc_gauss_weights": (I32, [P, I64, D, P, P]),
     "asc_gauss_weights_bwd_workspace": (SZ, [I64]),

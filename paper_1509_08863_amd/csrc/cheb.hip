@@ -73,22 +73,29 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         return ASC_OK;
     }
     const int grid = grid_for(n, P.lpr);
-    const size_t ckb = ckpt ? ck_block_bytes(n, r, sig) : 0;
+    // ckpt_stride >= 2: (T_sc, T_sc+1) pairs, row-major blocks; ckpt_stride == 1:
+    // every state in panel layout [slice][j][n x rs] (the recurrence writes its
+    // states straight into their slots, nothing is overwritten)
+    const bool store_all = ckpt && ckpt_stride == 1;
+    const size_t ckb = (ckpt && !store_all) ? ck_block_bytes(n, r, sig) : 0;
     auto ck_block = [&](int seg, int which) -> void * {
         return static_cast<char *>(ckpt) + ((size_t)seg * 2 + which) * ckb;
     };
-    const size_t panel_bytes = (size_t)n * P.rs * esize(sig);
-    (void)panel_bytes;
+    const size_t pbytes = panel_bytes(n, P.rs, sig);
+    auto slot = [&](int sl, int j) -> void * {
+        return static_cast<char *>(ckpt) + ((size_t)sl * (p + 1) + j) * pbytes;
+    };
     for (int sl = 0; sl < P.nslices; ++sl) {
         const int64_t c0 = (int64_t)sl * P.rs;
+        void *pa = store_all ? slot(sl, 0) : F.panelA;
+        void *pb = store_all ? slot(sl, 1) : F.panelB;
         {
             const int64_t tot = n * P.rs;
             const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
             if (sig == ASC_F32)
-                pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)F.panelA);
+                pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)pa);
             else
-                pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs,
-                                                         (uint16_t *)F.panelA);
+                pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)pa);
             ASC_LAUNCHED();
         }
         StepArgs A{};
@@ -103,16 +110,15 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         A.c0 = c0;
         A.r = r;
         A.coeffs = coeffs;
-        void *pa = F.panelA, *pb = F.panelB;  // pa holds T_j-1 .. ; cur alternates
-        // step 0: T_1 from T_0 (in A) into B
+        // step 0: T_1 from T_0
         A.cur = pa;
         A.prev = nullptr;
         A.out = pb;
         A.j = 0;
         A.partials = F.part;  // partial slot 0: first step
         A.ck_ld = ck_ld_of(r, sig);
-        A.ck_a = ckpt ? ck_block(0, 0) : nullptr;
-        A.ck_b = ckpt ? ck_block(0, 1) : nullptr;
+        A.ck_a = ckb ? ck_block(0, 0) : nullptr;
+        A.ck_b = ckb ? ck_block(0, 1) : nullptr;
         hipError_t e = launch_step(sig, P.lpr, P.var, M_FIRST | M_YACC | M_PART, A, grid, s);
         if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
         sum_partials_kernel<<<1, NT, 0, s>>>(grid, F.part, 1, 0, F.first);
@@ -120,12 +126,12 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         void *cur = pb, *prev = pa;
         for (int j = 1; j < p; ++j) {
             const bool last = (j == p - 1);
-            A.cur = cur;
-            A.prev = prev;
-            A.out = prev;  // T_{j+1} overwrites T_{j-1}
+            A.cur = store_all ? slot(sl, j) : cur;
+            A.prev = store_all ? slot(sl, j - 1) : prev;
+            A.out = store_all ? slot(sl, j + 1) : prev;  // else T_{j+1} overwrites T_{j-1}
             A.j = j;
             A.partials = F.part + (int64_t)kMaxGrid * 3;
-            const bool ck = ckpt && (j % ckpt_stride == 0);
+            const bool ck = ckb && (j % ckpt_stride == 0);
             A.ck_a = ck ? ck_block(j / ckpt_stride, 0) : nullptr;
             A.ck_b = ck ? ck_block(j / ckpt_stride, 1) : nullptr;
             e = launch_step(sig, P.lpr, P.var, M_YACC | (last ? M_PART : 0u), A, grid, s);
@@ -327,9 +333,13 @@ extern "C" size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int 
     return filter_ws(n, r, sig);
 }
 
-extern "C" size_t asc_ckpt_bytes(int64_t n, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
-    if (n < 1 || r < 1 || p < 0 || ckpt_stride < 2 || (sig != ASC_F32 && sig != ASC_BF16)) return 0;
-    return (size_t)nseg_of(p, ckpt_stride) * 2 * ck_block_bytes(n, r, sig);
+extern "C" size_t asc_ckpt_bytes(const asc_graph *g, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
+    if (!g || g->n < 1 || r < 1 || p < 0 || ckpt_stride < 1 || (sig != ASC_F32 && sig != ASC_BF16)) return 0;
+    if (ckpt_stride == 1) {
+        const Plan P = make_plan(g, r, sig);
+        return (size_t)P.nslices * (p + 1) * panel_bytes(g->n, P.rs, sig);
+    }
+    return (size_t)nseg_of(p, ckpt_stride) * 2 * ck_block_bytes(g->n, r, sig);
 }
 
 extern "C" asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax, int p, int jackson,
@@ -359,8 +369,8 @@ extern "C" asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, co
         const char *ye = yb + (size_t)((g->n - 1) * ldy + r) * 4;
         if (rb < ye && yb < re) return fail(ASC_ERR_INVALID, "%s: Y overlaps R", who);
     }
-    if (ckpt && (ckpt_stride < 2 || !aligned(ckpt, 256)))
-        return fail(ASC_ERR_INVALID, "%s: ckpt needs ckpt_stride >= 2 and 256-byte alignment", who);
+    if (ckpt && (ckpt_stride < 1 || !aligned(ckpt, 256)))
+        return fail(ASC_ERR_INVALID, "%s: ckpt needs ckpt_stride >= 1 and 256-byte alignment", who);
     ASC_TRY(check_ws(ws, ws_bytes, asc_filter_workspace(g->n, r, sig, p), who));
     return run_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, ckpt, ckpt_stride, ws, true, as_stream(stream));
 }
@@ -514,7 +524,7 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
             void *cur = F.panelA, *prev = F.panelB;
             float ms = 0.f;
             for (int it = -1; it < probe_steps; ++it) {
-                if (it == 0) hipEventRecord(e0, s);
+                if (it == 0) (void)hipEventRecord(e0, s);
                 for (int sl = 0; sl < P.nslices; ++sl) {
                     A.c0 = (int64_t)sl * P.rs;
                     A.cur = cur;
@@ -529,9 +539,9 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
                 std::swap(cur, prev);
             }
             if (st != ASC_OK) break;
-            hipEventRecord(e1, s);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
             ms /= (float)std::max(1, probe_steps);
             if (ms < bestE.ms) {
                 bestE.ms = ms;
@@ -541,8 +551,8 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
         }
         if (st != ASC_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != ASC_OK) return st;
     bestE.key = TuneKey{n, g->nnz, r, (int)sig};
     {
@@ -615,7 +625,6 @@ extern "C" asc_status asc_tune_load(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(ASC_ERR_INVALID, "asc_tune_load: cannot open %s", path);
     char line[512];
-    int loaded = 0;
     while (fgets(line, sizeof line, f)) {
         long long n, nnz, r;
         int dt, rs, var;
@@ -624,7 +633,6 @@ extern "C" asc_status asc_tune_load(const char *path) {
                    &n, &nnz, &r, &dt, &rs, &var, &ms) == 7) {
             if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && (var == 0 || var == 1)) {
                 asc_tune_set(n, nnz, r, (asc_dtype)dt, rs, var);
-                ++loaded;
             }
         }
     }
@@ -646,5 +654,141 @@ extern "C" asc_status asc_autotune_filter(const asc_graph *g, const double *lmax
     if (best_slice_cols) *best_slice_cols = e.rs;
     if (best_variant) *best_variant = e.var;
     if (best_ms_per_step) *best_ms_per_step = e.ms;
+    return ASC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one-pass lambda_k + filter: states are kept, Y is formed at the end
+// ---------------------------------------------------------------------------
+namespace asc {
+namespace {
+
+// Y[i, c0 + c] = sum_j a_j T_j[i, c] over the stored panels of one slice;
+// one thread per 16-byte chunk, coefficients summed in order j = 0..p
+template <typename TS>
+__global__ void combine_kernel(int64_t n, int rs, const TS *__restrict__ slots, int64_t slot_elems, int p,
+                               const double *__restrict__ coeffs, float *__restrict__ Y, int64_t ldy, int64_t c0,
+                               int64_t r) {
+    constexpr int VN = St<TS>::VN;
+    const int64_t chunks = n * (rs / VN);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / (rs / VN);
+        const int cc = (int)(q - i * (rs / VN)) * VN;
+        float acc[VN];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[e] = 0.0f;
+        const TS *src = slots + i * rs + cc;
+        for (int j = 0; j <= p; ++j) fma_raw(acc, (float)coeffs[j], ldraw<true>(src + (int64_t)j * slot_elems));
+        float *y = Y + i * ldy + c0 + cc;
+        if (c0 + cc + VN <= r) {
+#pragma unroll
+            for (int e = 0; e < VN; e += 4) {
+                v4f v = {acc[e], acc[e + 1], acc[e + 2], acc[e + 3]};
+                *reinterpret_cast<v4f *>(y + e) = v;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < VN; ++e)
+                if (c0 + cc + e < r) y[e] = acc[e];
+        }
+    }
+}
+
+size_t lkf_ws_layout(int64_t n, int64_t r, asc_dtype sig, int p, void *ws, void **mws, double **mu, double **co) {
+    Arena a(ws);
+    void *m = a.take<char>(moments_ws(n, r, sig, p));
+    double *u = a.take<double>(p + 1);
+    double *c = a.take<double>(p + 1);
+    if (mws) *mws = m;
+    if (mu) *mu = u;
+    if (co) *co = c;
+    return a.size();
+}
+
+}  // namespace
+}  // namespace asc
+
+extern "C" size_t asc_lambda_k_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p) {
+    return lkf_ws_layout(n, r, sig, p, nullptr, nullptr, nullptr, nullptr);
+}
+
+extern "C" asc_status asc_lambda_k_filter(const asc_graph *g, const double *lmax, int k, int p, int steps,
+                                          const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
+                                          double *lambda_k, double *traj, double *coeffs_out, void *states, void *ws,
+                                          size_t ws_bytes, void *stream) {
+    const char *who = "asc_lambda_k_filter";
+    ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
+    if (p < 1) return fail(ASC_ERR_INVALID, "%s: p must be >= 1", who);
+    ASC_TRY(check_block(Y, ASC_F32, g->n, r, ldy, who, "Y"));
+    if (!lambda_k || !aligned(lambda_k, 8) || (traj && !aligned(traj, 8)) || (coeffs_out && !aligned(coeffs_out, 8)))
+        return fail(ASC_ERR_INVALID, "%s: lambda_k NULL or outputs misaligned", who);
+    if (k < 0 || steps < 0 || steps > 200) return fail(ASC_ERR_INVALID, "%s: k=%d steps=%d", who, k, steps);
+    if (!states || !aligned(states, 256)) return fail(ASC_ERR_INVALID, "%s: states NULL or not 256-byte aligned", who);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_lambda_k_filter_workspace(g->n, r, sig, p), who));
+    hipStream_t s = as_stream(stream);
+    const int64_t n = g->n;
+    void *mws;
+    double *mu, *co;
+    lkf_ws_layout(n, r, sig, p, ws, &mws, &mu, &co);
+    if (coeffs_out) co = coeffs_out;
+    const Plan P = make_plan(g, r, sig);
+    const int msteps = std::max(1, (p + 1) / 2);
+    FilterWs F;
+    filter_ws_layout(n, rs_for_ws(r, sig), (int)((r + 2 * vn_of(sig) - 1) / (2 * vn_of(sig))), sig, msteps, msteps,
+                     mws, &F);
+    uint32_t *flags = &F.hdr->flags;
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, flags, 1);
+    ASC_LAUNCHED();
+    const int grid = grid_for(n, P.lpr);
+    const size_t pbytes = panel_bytes(n, P.rs, sig);
+    auto slot = [&](int sl, int j) -> void * { return static_cast<char *>(states) + ((size_t)sl * (p + 1) + j) * pbytes; };
+    const int64_t tot = n * P.rs;
+    const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    for (int sl = 0; sl < P.nslices; ++sl) {
+        const int64_t c0 = (int64_t)sl * P.rs;
+        if (sig == ASC_F32)
+            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)slot(sl, 0));
+        else
+            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)slot(sl, 0));
+        ASC_LAUNCHED();
+        StepArgs A{};
+        A.n = n;
+        A.rp = g->row_ptr;
+        A.ci = g->col_idx;
+        A.w = g->w;
+        A.diag = F.diag;
+        A.beta = F.beta;
+        for (int j = 0; j < p; ++j) {
+            A.cur = slot(sl, j);
+            A.prev = j == 0 ? nullptr : slot(sl, j - 1);
+            A.out = slot(sl, j + 1);
+            A.j = j;
+            const bool part = j < msteps;
+            A.partials = part ? F.part + (int64_t)j * kMaxGrid * 3 : nullptr;
+            hipError_t e = launch_step(sig, P.lpr, P.var, (j == 0 ? M_FIRST : 0u) | (part ? M_PART : 0u), A, grid, s);
+            if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+        }
+        sum_partials_kernel<<<msteps, NT, 0, s>>>(grid, F.part, msteps, (int64_t)kMaxGrid * 3,
+                                                  F.sums + (int64_t)sl * msteps * 3);
+        ASC_LAUNCHED();
+    }
+    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, P.nslices, msteps, p, mu, flags);
+    ASC_LAUNCHED();
+    dichotomy_kernel<<<1, NT, 0, s>>>(mu, p, lmax, k, steps, 1, lambda_k, traj);
+    ASC_LAUNCHED();
+    coeffs_kernel<<<(p + 256) / 256, 256, 0, s>>>(lambda_k, 1, lmax, p, 1, co);
+    ASC_LAUNCHED();
+    const int64_t chunks = n * (P.rs / vn_of(sig));
+    const int cg = (int)std::min<int64_t>((chunks + 255) / 256, 65536);
+    for (int sl = 0; sl < P.nslices; ++sl) {
+        const int64_t slot_elems = (int64_t)(pbytes / esize(sig));
+        if (sig == ASC_F32)
+            combine_kernel<float><<<cg, 256, 0, s>>>(n, P.rs, (const float *)slot(sl, 0), slot_elems, p, co, Y, ldy,
+                                                     (int64_t)sl * P.rs, r);
+        else
+            combine_kernel<uint16_t><<<cg, 256, 0, s>>>(n, P.rs, (const uint16_t *)slot(sl, 0), slot_elems, p, co, Y,
+                                                        ldy, (int64_t)sl * P.rs, r);
+        ASC_LAUNCHED();
+    }
     return ASC_OK;
 }

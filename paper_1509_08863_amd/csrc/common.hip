@@ -1,6 +1,8 @@
 // Error reporting, argument validation and the small utility entry points.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace asc {
 
 std::string &last_error_ref() {
@@ -72,5 +74,26 @@ extern "C" asc_status asc_read_flags(const void *ws, uint32_t *flags_host, void 
     if (f & ASC_FLAG_NONFINITE) return fail(ASC_ERR_NONFINITE, "non-finite value in a filtered block");
     if (f & ASC_FLAG_GROWTH)
         return fail(ASC_ERR_LMAX_TOO_SMALL, "recurrence grew: |T_p R| > 1.5 |R|, lambda_max is below lambda_N");
+    return ASC_OK;
+}
+
+// plain streaming copy (16-byte vectors), the reference kernel for bandwidth
+// and memory-counter calibration
+namespace {
+__global__ void stream_copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+}  // namespace
+
+extern "C" asc_status asc_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16 || !aligned(src, 16) || !aligned(dst, 16))
+        return fail(ASC_ERR_INVALID, "asc_stream_copy: pointers must be 16-byte aligned and bytes a multiple of 16");
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int grid = (int)std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    if (n16 == 0) return ASC_OK;
+    stream_copy_kernel<<<grid, 256, 0, as_stream(stream)>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst),
+                                                             n16);
+    ASC_LAUNCHED();
     return ASC_OK;
 }

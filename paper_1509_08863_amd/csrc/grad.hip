@@ -456,7 +456,7 @@ extern "C" asc_status asc_rownorm_loss_bwd(const float *Y, int64_t ldy, const fl
 }
 
 extern "C" size_t asc_filter_bwd_workspace(int64_t n, int64_t nnz, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
-    if (ckpt_stride < 2) ckpt_stride = 2;
+    if (ckpt_stride < 1) ckpt_stride = 1;
     return bwd_ws_layout(n, nnz, r, sig, p, ckpt_stride, nullptr, nullptr);
 }
 
@@ -468,11 +468,12 @@ extern "C" asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax
     ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
     if (!coeffs || !aligned(coeffs, 8)) return fail(ASC_ERR_INVALID, "%s: coeffs NULL or misaligned", who);
     ASC_TRY(check_block(G, ASC_F32, g->n, r, ldg, who, "G"));
-    if (p >= 1 && (!ckpt || ckpt_stride < 2 || !aligned(ckpt, 256)))
-        return fail(ASC_ERR_INVALID, "%s: needs the forward checkpoints (ckpt_stride >= 2)", who);
+    if (p >= 1 && (!ckpt || ckpt_stride < 1 || !aligned(ckpt, 256)))
+        return fail(ASC_ERR_INVALID, "%s: needs the forward checkpoints (ckpt_stride >= 1)", who);
     if (dW && !aligned(dW, 4)) return fail(ASC_ERR_INVALID, "%s: dW misaligned", who);
     if (dcoeffs && !aligned(dcoeffs, 8)) return fail(ASC_ERR_INVALID, "%s: dcoeffs misaligned", who);
-    const int c = std::max(2, ckpt_stride);
+    const int c = std::max(1, ckpt_stride);
+    const bool store_all = c == 1;
     ASC_TRY(check_ws(ws, ws_bytes, asc_filter_bwd_workspace(g->n, g->nnz, r, sig, p, c), who));
     hipStream_t s = as_stream(stream);
     const int64_t n = g->n, nnz = g->nnz;
@@ -546,6 +547,40 @@ extern "C" asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax
         A.r = r;
         A.mt = B.mt;
         A.mdiag = B.mdiag;
+        if (store_all) {
+            // every state is in the store: slot(sl, j) = T_j of this slice
+            const size_t spb = panel_bytes(n, P.rs, sig);
+            auto slot = [&](int j) -> const void * {
+                return static_cast<const char *>(ckpt) + ((size_t)sl * (p + 1) + j) * spb;
+            };
+            if (sig == ASC_F32)
+                adj_init_kernel<float><<<grid, NT, 0, s>>>(n, G, ldg, c0, r, P.rs, coeffs, p, (const float *)slot(p),
+                                                           (float *)Acur, B.dapart + (int64_t)p * kMaxGrid);
+            else
+                adj_init_kernel<uint16_t><<<grid, NT, 0, s>>>(n, G, ldg, c0, r, P.rs, coeffs, p,
+                                                              (const uint16_t *)slot(p), (uint16_t *)Acur,
+                                                              B.dapart + (int64_t)p * kMaxGrid);
+            ASC_LAUNCHED();
+            for (int j = p - 1; j >= 0; --j) {
+                A.acur = Acur;
+                A.aold = Aold;
+                A.aout = Aold;
+                A.tj = slot(j);
+                A.cj = (j == 0) ? 1.0f : 2.0f;
+                A.partials = B.dapart + (int64_t)j * kMaxGrid;
+                unsigned mode = B_DA | (want_dw ? B_DW : 0u);
+                if (j >= 1) mode |= B_OUT;
+                if (j == p - 1) mode |= B_TOP;
+                A.coeffs = coeffs;
+                A.j = j;
+                hipError_t e = launch_adj(sig, P.lpr, mode, A, grid, s);
+                if (e != hipSuccess) return fail(ASC_ERR_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
+                std::swap(Acur, Aold);
+            }
+            da_accum_kernel<<<p + 1, NT, 0, s>>>(B.dapart, grid, kMaxGrid, p, B.dsum);
+            ASC_LAUNCHED();
+            continue;
+        }
         for (int seg = nseg - 1; seg >= 0; --seg) {
             const int sc = seg * c;
             const int hi = std::min(sc + c, p);

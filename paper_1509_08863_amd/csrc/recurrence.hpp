@@ -468,6 +468,7 @@ int64_t ck_ld_of(int64_t r, asc_dtype dt) {
     return (r + w - 1) / w * w;
 }
 int nseg_of(int p, int c) { return p <= 0 ? 0 : (p + c - 1) / c; }
+size_t panel_bytes(int64_t n, int rs, asc_dtype dt) { return ((size_t)n * rs * esize(dt) + 255) & ~size_t(255); }
 size_t ck_block_bytes(int64_t n, int64_t r, asc_dtype dt) {
     return ((size_t)n * ck_ld_of(r, dt) * esize(dt) + 255) & ~size_t(255);
 }

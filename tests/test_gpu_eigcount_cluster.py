@@ -132,3 +132,25 @@ def test_kmeans_init_rows():
     rows = np.array([3, 50, 99], dtype=np.int32)
     C = asc.kmeans_init_rows(block_f32(F), to_dev(rows))
     np.testing.assert_array_equal(host(C), F[rows])
+
+
+@pytest.mark.parametrize("r,p", [(32, 50), (33, 51), (8, 1)])
+def test_one_pass_lambda_k_filter(r, p):
+    g = W.config_graph(1)
+    L, lmax = _setup(g, p)
+    G = upload_graph(g)
+    Rs, R64 = W.signals(g.n, r, 13)
+    k, steps = 10, 12
+    Y, lam, traj, co, states = asc.lambda_k_filter(G, scalar(lmax), k, p, steps, block_f32(Rs))
+    # the same moments and decisions as the two-pass entry points
+    lam2, traj2 = asc.eigcount_lambda_k(G, scalar(lmax), k, p, steps, block_f32(Rs))
+    np.testing.assert_array_equal(host(traj), host(traj2))
+    Y2 = asc.cheb_filter(G, scalar(lmax), asc.cheb_coeffs(lam2, scalar(lmax), p), block_f32(Rs))
+    assert rel_fro(host(Y), host(Y2)) <= 1e-6
+    np.testing.assert_array_equal(host(co), host(asc.cheb_coeffs(lam, scalar(lmax), p))[0])
+    # against the oracle (same decisions up to a near tie)
+    est_ref, traj_ref = oracle.dichotomy_moments(L, lmax, k, p, steps, R64)
+    _traj_agree(host(traj), traj_ref, k, 1e-3)
+    if np.all(np.abs(traj_ref[:, 1] - (k - 0.5)) > 1e-3):
+        Yref = oracle.cheb_filter(L, lmax, oracle.cheb_coeffs(est_ref, lmax, p), R64)
+        assert rel_fro(host(Y), Yref) <= 1e-5

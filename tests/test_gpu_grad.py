@@ -133,3 +133,22 @@ def test_bwd_deterministic_and_bf16_runs():
     print("bf16 bwd rel dW", rel_fro(host(dW), dw_ref), "rel da", rel_fro(host(dc), da_ref))
     assert rel_fro(host(dW), dw_ref) <= 0.1
     assert rel_fro(host(dc), da_ref) <= 0.1
+
+
+@pytest.mark.parametrize("r,p", [(16, 30), (40, 7), (5, 1)])
+def test_state_store_forward_and_backward_equal_checkpoint_path(r, p):
+    g, w64, L, lmax, a, Rs, R64, T = _problem(n=1500, r=r, p=p)
+    Gd = upload_graph(g, w=w64.astype(np.float32))
+    G64 = W.signals_f64(g.n, r, 5).astype(np.float32).astype(np.float64)
+    Rd = block_f32(Rs)
+    Y1, ck1 = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=1)
+    Y3, ck3 = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=3)
+    np.testing.assert_array_equal(host(Y1), host(Y3))
+    d1 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, ck1, 1, block_f32(G64))]
+    d3 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, ck3, 3, block_f32(G64))]
+    np.testing.assert_array_equal(d1[0], d3[0])
+    np.testing.assert_array_equal(d1[1], d3[1])
+    w32 = w64.astype(np.float32).astype(np.float64)
+    dw_ref, da_ref = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w32, lmax, a, R64, G64)
+    assert rel_fro(d1[0], dw_ref) <= TOL_DW
+    assert rel_fro(d1[1], da_ref) <= TOL_DA
