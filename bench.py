@@ -33,6 +33,35 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
+# Memory traffic of the step kernel (cheb_step<float, 8, 2u, 0u>: one 32-column
+# slice of the 1M-node SBM, weights stored), from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (KiB per dispatch), scaled by the same counters on the plain
+# 2 GiB copy kernel (FETCH_SIZE reads 1 GiB for 2 GiB read -> x2.0; WRITE_SIZE
+# reads 2 GiB -> x1.0).  Valid only while the kernel source is the one measured
+# (sha1 of the step-kernel region of recurrence.hpp); otherwise reported null.
+STEP_TRAFFIC = {
+    "src_sha1": "284df45145f1feb636e2f69884a2ce76b9883381",
+    "workload": "sbm_n1e6_k50dir_d30_r96_p150",
+    "fetch_kib_per_launch": 2233118.06, "write_kib_per_launch": 250000.0,
+    "fetch_scale": 2.0, "write_scale": 1.0, "launches_per_unit": 3,
+}
+
+
+def step_kernel_sha1():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1509_08863_amd", "csrc", "recurrence.hpp")).read()
+    a = src.index("// One row of a recurrence step")
+    b = src.index("// d_i = 4 s_i / lmax - 2")
+    return hashlib.sha1(src[a:b].encode()).hexdigest()
+
+
+def step_traffic_bytes(workload, slice_cols, launches):
+    t = STEP_TRAFFIC
+    if step_kernel_sha1() != t["src_sha1"] or workload != t["workload"] or slice_cols != 32 or launches != 3:
+        return None
+    per_launch = 1024 * (t["fetch_kib_per_launch"] * t["fetch_scale"] + t["write_kib_per_launch"] * t["write_scale"])
+    return per_launch * t["launches_per_unit"]
+
 
 def b_step(n, nnz, r, bt, weighted=True):
     return 4 * (n + 1) + nnz * (4 + (4 if weighted else 0)) + 4 * n + 3 * n * r * bt + 2 * n * r * 4
@@ -258,7 +287,8 @@ def main():
         "lambda_max": lmax_h,
         "lambda_k_est": lam_k_h,
         "roofline": {"bound": "hbm", "achieved": round(gbs32, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs32 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs32 / HBM_PEAK_GBS, 4),
+                     "traffic": step_traffic_bytes(cfg["name"], tuned.get("f32", (32,))[0], -(-r // 32)),
                      "kernel": "cheb_step", "unit_bytes": bs32, "units_per_filter": steps_per_filter},
         "cpu_baseline": cpu,
         "gen_s": round(gen_s, 1),
