@@ -67,6 +67,105 @@ def b_step(n, nnz, r, bt, weighted=True):
     return 4 * (n + 1) + nnz * (4 + (4 if weighted else 0)) + 4 * n + 3 * n * r * bt + 2 * n * r * 4
 
 
+def _time(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extra_knn(dev):
+    """Gaussian-mixture 10-NN graph, N = 2e5, R = 64, p = 100: lambda_k + filter
+    in one pass, forward+backward through the autograd wrappers (sigma, weights,
+    coefficients), as generated and with a locality (RCM) node order."""
+    import torch
+    import paper_1509_08863_amd as asc
+    from paper_1509_08863_amd.autograd import ChebFilter, GaussWeights, RowNormLoss
+    cfg = W.CONFIGS[5]
+    seeds = W.config_seeds(5)
+    g0 = W.config_graph(5)
+    r, p, k, sigma = cfg["r"], cfg["p"], cfg["k"], cfg["sigma"]
+    out = {"workload": cfg["name"], "n": g0.n, "nnz": g0.nnz}
+    for order in ("generated", "rcm"):
+        t0 = time.time()
+        g = g0 if order == "generated" else W.locality_order(g0)[0]
+        prep_s = time.time() - t0
+        d2 = torch.from_numpy(g.d2).to(dev)
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        ci = torch.from_numpy(g.col_idx).to(dev)
+        w = asc.gauss_weights(d2, sigma)
+        G = asc.graph_prepare(rp, ci, w)
+        lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, seeds["lanczos"])).to(dev), 60)
+        R = torch.from_numpy(W.signals(g.n, r, seeds["signals"])[0]).to(dev)
+        T = torch.from_numpy(W.unit_rows(g.n, r, seeds["target"])).to(dev)
+        tuned = asc.autotune_filter(G, lmax, R, 3)
+        Y = torch.empty(g.n, r, dtype=torch.float32, device=dev)
+        states = asc.workspace(asc._abi.lib().asc_ckpt_bytes(G.c(), r, asc.ASC_F32, p, 1), dev)
+        res = {}
+        res["ms_lambda_k_filter_one_pass"] = _time(lambda: asc.lambda_k_filter(G, lmax, k, p, 12, R, Y, states))
+        _, lam_k, _, a, _ = asc.lambda_k_filter(G, lmax, k, p, 12, R, Y, states)
+        res["ms_filter_fwd"] = _time(lambda: asc.cheb_filter(G, lmax, a, R, Y))
+        sig = torch.tensor(sigma, dtype=torch.float64, device=dev, requires_grad=True)
+        co = a.reshape(-1).clone().requires_grad_(True)
+
+        def fwd_bwd():
+            ww = GaussWeights.apply(d2, sig)
+            Yf = ChebFilter.apply(ww, co, rp, ci, lmax, R, 1)
+            loss = RowNormLoss.apply(Yf, T)
+            loss.backward()
+            return loss
+
+        res["ms_fwd_bwd_autograd"] = _time(fwd_bwd)
+        bs = b_step(g.n, g.nnz, r, 4)
+        res["filter_gbs"] = round(p * bs / (res["ms_filter_fwd"] * 1e-3) / 1e9, 1)
+        res["tuned"] = {"slice_cols": tuned[0], "variant": tuned[1]}
+        res["reorder_host_s"] = round(prep_s, 3)
+        out[order] = {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in res.items()}
+    return out
+
+
+def extra_batch(dev):
+    """64 SBMs, N log-uniform in [2e3, 2e5], k in 5..40, mean degree 10-30,
+    R = 48, p = 80, 8 dichotomy steps, one captured launch."""
+    import torch
+    import paper_1509_08863_amd as asc
+    cfg = W.CONFIGS[4]
+    r, p, steps = cfg["r"], cfg["p"], cfg["trials"]
+    t0 = time.time()
+    gs = W.batch_graphs()
+    ks = np.array([g.k for g in gs], dtype=np.int32)
+    lm = []
+    for q, g in enumerate(gs):
+        Gq = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev), None)
+        lm.append(asc.lmax_estimate(Gq, torch.from_numpy(W.start_vector(g.n, 500 + q)).to(dev), 60))
+    lmax = torch.cat(lm)
+    big, off = W.concat_graphs(gs)
+    gen_s = time.time() - t0
+    G = asc.graph_prepare(torch.from_numpy(big.row_ptr).to(dev), torch.from_numpy(big.col_idx).to(dev),
+                          torch.from_numpy(big.w).to(dev))
+    R = torch.from_numpy(W.signals(big.n, r, 4041)[0]).to(dev)
+    Y = torch.empty(big.n, r, dtype=torch.float32, device=dev)
+    lam = torch.empty(len(gs), dtype=torch.float64, device=dev)
+    traj = torch.empty(len(gs), steps, 2, dtype=torch.float64, device=dev)
+    B = asc.Batch(G, off, ks, r, torch.float32, p, steps)
+    ms_graph = _time(lambda: B.run(lmax, R, Y, lam, traj, use_graph=True))
+    ms_eager = _time(lambda: B.run(lmax, R, Y, lam, traj, use_graph=False))
+    ms_steps = max(1, (p + 1) // 2)
+    byts = ms_steps * (b_step(big.n, big.nnz, r, 4) - 8 * big.n * r) + p * b_step(big.n, big.nnz, r, 4)
+    info = B.info()
+    B.close()
+    return {"workload": cfg["name"], "graphs": len(gs), "n_total": big.n, "nnz_total": big.nnz,
+            "ms_per_batch_graph": round(ms_graph, 3), "ms_per_batch_eager": round(ms_eager, 3),
+            "gbs": round(byts / (ms_graph * 1e-3) / 1e9, 1), "algorithmic_bytes": byts, "plan": info,
+            "gen_s": round(gen_s, 1)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +362,9 @@ def main():
                              f"{cpu_s:.1f} s; scaled by {r}/{cols} to one filter"}
 
     steps_per_filter = p
+    extra = None
+    if args.extra:
+        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev)}
     line = {
         "metric": "Chebyshev-filter SpMM HBM GB/s + ms/filter (fwd, fwd+bwd) at err vs FP64",
         "value": round(gbs32, 2),
@@ -291,6 +393,7 @@ def main():
                      "traffic": step_traffic_bytes(cfg["name"], tuned.get("f32", (32,))[0], -(-r // 32)),
                      "kernel": "cheb_step", "unit_bytes": bs32, "units_per_filter": steps_per_filter},
         "cpu_baseline": cpu,
+        "extra": extra,
         "gen_s": round(gen_s, 1),
     }
     print(json.dumps(line))

@@ -270,8 +270,11 @@ asc_status asc_batch_destroy(void *plan);
  *   slice_cols: columns processed per pass (float32: 8, 16, 32, 64;
  *               bfloat16: 16, 32, 64, 128); 0 in asc_tune_set removes the
  *               entry.
- *   variant:    0 = plain loads; 1 = non-temporal hints on the streamed
- *               arrays (CSR, T_{j-1}, Y) so that the gathered block stays cached.
+ *   variant:    bit 0: non-temporal hints on the streamed arrays (CSR,
+ *               T_{j-1}, Y) so that the gathered block stays cached; bit 1:
+ *               the lanes of a row load the next 8 column indices / weights
+ *               with one coalesced request and broadcast them in the row
+ *               group (fewer vector-memory requests per neighbour).
  * asc_autotune_filter times every candidate on the caller's graph and signals
  * for probe_steps recurrence steps (Y and ws are scratch; needs ws of
  * asc_filter_workspace(n, r, sig, 1) bytes), records the fastest and returns

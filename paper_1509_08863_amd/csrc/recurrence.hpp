@@ -139,41 +139,86 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
 #pragma unroll
     for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
     const TS *base = cur + t * VN;
-    // padding slots gather the row itself with weight 0
-    int32_t kn[U];
-    float wn[U];
+    if constexpr ((VAR & 2u) != 0) {
+        // cooperative index loads: the lanes of the row group load the next U
+        // column indices / weights with one coalesced request (M per lane) and
+        // broadcast them inside the group, instead of every lane loading all U
+        constexpr int M = (LPR >= U) ? 1 : U / LPR;
+        const int gbase = (int)(threadIdx.x & 63) & ~(LPR - 1);
+        int32_t mk[M];
+        float mw[M];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        kn[u] = (int32_t)row;
-        wn[u] = 0.0f;
-        if (e0 + u < e1) {
-            kn[u] = ldx<NTH>(A.ci + e0 + u);
-            wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
+        for (int m = 0; m < M; ++m) {
+            const int32_t ee = e0 + t + LPR * m;
+            mk[m] = (int32_t)row;
+            mw[m] = 0.0f;
+            if ((LPR < U || t < U) && ee < e1) {
+                mk[m] = ldx<NTH>(A.ci + ee);
+                mw[m] = weighted ? ldx<NTH>(A.w + ee) : 1.0f;
+            }
         }
-    }
-    for (int32_t e = e0; e < e1; e += U) {
-        int32_t kc[U];
-        float wc[U];
+        for (int32_t e = e0; e < e1; e += U) {
+            int32_t kc[U];
+            float wc[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            kc[u] = kn[u];
-            wc[u] = wn[u];
+            for (int u = 0; u < U; ++u) {
+                const int src = gbase + (LPR < U ? (u % LPR) : u);
+                kc[u] = __shfl(mk[LPR < U ? u / LPR : 0], src, 64);
+                wc[u] = __shfl(mw[LPR < U ? u / LPR : 0], src, 64);
+            }
+            raw_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int32_t ee = e + U + t + LPR * m;
+                mk[m] = (int32_t)row;
+                mw[m] = 0.0f;
+                if ((LPR < U || t < U) && ee < e1) {
+                    mk[m] = ldx<NTH>(A.ci + ee);
+                    mw[m] = weighted ? ldx<NTH>(A.w + ee) : 1.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
         }
-        raw_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
-        const int32_t en = e + U;
+    } else {
+        // padding slots gather the row itself with weight 0
+        int32_t kn[U];
+        float wn[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             kn[u] = (int32_t)row;
             wn[u] = 0.0f;
-            if (en + u < e1) {
-                kn[u] = ldx<NTH>(A.ci + en + u);
-                wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
+            if (e0 + u < e1) {
+                kn[u] = ldx<NTH>(A.ci + e0 + u);
+                wn[u] = weighted ? ldx<NTH>(A.w + e0 + u) : 1.0f;
             }
         }
+        for (int32_t e = e0; e < e1; e += U) {
+            int32_t kc[U];
+            float wc[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+            for (int u = 0; u < U; ++u) {
+                kc[u] = kn[u];
+                wc[u] = wn[u];
+            }
+            raw_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+            const int32_t en = e + U;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kn[u] = (int32_t)row;
+                wn[u] = 0.0f;
+                if (en + u < e1) {
+                    kn[u] = ldx<NTH>(A.ci + en + u);
+                    wn[u] = weighted ? ldx<NTH>(A.w + en + u) : 1.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+        }
     }
     float own[VN], nxt[VN], stv[VN];
     const raw_t own_raw = ldraw(cur + row * RS + t * VN);
@@ -435,8 +480,12 @@ hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t
 
 template <typename TS, int LPR>
 hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int grid, hipStream_t s) {
-    if (var & 1u) return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
-    return launch_step_v<TS, LPR, 0u>(mode, A, grid, s);
+    switch (var & 3u) {
+        case 1u: return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
+        case 2u: return launch_step_v<TS, LPR, 2u>(mode, A, grid, s);
+        case 3u: return launch_step_v<TS, LPR, 3u>(mode, A, grid, s);
+        default: return launch_step_v<TS, LPR, 0u>(mode, A, grid, s);
+    }
 }
 
 hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const StepArgs &A, int grid,

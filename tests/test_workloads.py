@@ -64,3 +64,25 @@ def test_named_graphs():
     for g in (W.complete(5), W.cycle(7), W.path(4), W.star(6), W.cliques(3, 4, True),
               W.random_weighted(20, 0.3, 1, isolated=2)):
         _check_csr(g)
+
+
+def test_locality_order_is_a_relabelling():
+    import oracle
+    g = W.gmm_knn(1500, 16, 5, 10, 3)
+    h, perm = W.locality_order(g)
+    _check_csr(h)
+    assert sorted(perm.tolist()) == list(range(g.n))
+    w_g = oracle.gauss_weights(g.d2.astype(np.float64), 2.0)
+    w_h = oracle.gauss_weights(h.d2.astype(np.float64), 2.0)
+    Lg = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w_g)
+    Lh = oracle.laplacian_sparse(h.n, h.row_ptr, h.col_idx, w_h)
+    assert abs(Lg[perm][:, perm] - Lh).max() <= 1e-12  # strengths summed in another order
+    # the filter commutes with the relabelling
+    R = W.signals_f64(g.n, 4, 2)
+    a = oracle.cheb_coeffs(1.0, 20.0, 30)
+    np.testing.assert_allclose(oracle.cheb_filter(Lh, 20.0, a, R[perm]), oracle.cheb_filter(Lg, 20.0, a, R)[perm],
+                               rtol=1e-12, atol=1e-14)
+    # neighbours end up closer in index space
+    rows_g = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    rows_h = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+    assert np.abs(rows_h - h.col_idx).mean() < 0.5 * np.abs(rows_g - g.col_idx).mean()

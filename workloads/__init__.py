@@ -379,3 +379,21 @@ def concat_graphs(graphs):
         w[nnz_off[q]: nnz_off[q + 1]] = g.weights_or_ones()
     big = Graph(n=int(off[-1]), row_ptr=rp.astype(np.int32), col_idx=ci.astype(np.int32), w=w)
     return big, off
+
+
+def locality_order(g: Graph):
+    """(permuted Graph, perm) with nodes in reverse Cuthill-McKee order
+    (perm[new] = old), a bandwidth-reducing relabelling that keeps graph
+    neighbours close in index space.  Data-layout preprocessing only: the
+    graph is the same up to relabelling."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    A = sp.csr_matrix((np.arange(1, g.nnz + 1, dtype=np.int64), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    perm = reverse_cuthill_mckee(A, symmetric_mode=True).astype(np.int64)
+    B = A[perm][:, perm].tocsr()
+    B.sort_indices()
+    src = B.data - 1  # position of each new entry in the old arrays
+    out = Graph(n=g.n, row_ptr=B.indptr.astype(np.int32), col_idx=B.indices.astype(np.int32),
+                w=None if g.w is None else g.w[src], d2=None if g.d2 is None else g.d2[src],
+                labels=None if g.labels is None else g.labels[perm], k=g.k)
+    return out, perm
