@@ -31,4 +31,4 @@ from .eigcount import (moments, eigcount_from_moments, eigcount_literal,  # noqa
                        exact_count, dichotomy, dichotomy_moments, dichotomy_literal)
 from .cluster import normalize_rows, kmeans_assign, kmeans_update, kmeans_lloyd  # noqa: F401
 from .grad import (gauss_weights, rownorm_loss_grad, cheb_filter_adjoint,  # noqa: F401
-                   daleckii_krein_M, dW_from_M, dsigma, loss_of_weights)
+                   daleckii_krein_M, dW_from_M, dsigma, loss_of_weights, cheb_filter_adjoint_sampled)

@@ -129,3 +129,39 @@ def loss_of_weights(n, row_ptr, col_idx, w, lmax, a, R, T):
     L = _operator(n, row_ptr, col_idx, w)
     Y = cheb_filter(L, lmax, a, R)
     return rownorm_loss_grad(Y, T)[0]
+
+
+def cheb_filter_adjoint_sampled(n, row_ptr, col_idx, w, lmax, a, R, G, entries):
+    """Like cheb_filter_adjoint, but dw only for the stored entries `entries`
+    (indices into col_idx): the recurrences run at full size while only the
+    rows that the sampled M_ii and M_ik need are kept, so large graphs fit.
+    Returns (dw[entries], da)."""
+    a = np.asarray(a, dtype=np.float64)
+    p = len(a) - 1
+    entries = np.asarray(entries, dtype=np.int64)
+    rows_all = np.repeat(np.arange(n), np.diff(np.asarray(row_ptr, dtype=np.int64)))
+    ri = rows_all[entries]
+    ck = np.asarray(col_idx, dtype=np.int64)[entries]
+    L = _operator(n, row_ptr, col_idx, w)
+    Lt = scaled_laplacian(L, lmax)
+    LtT = Lt.T.tocsr()
+    G = np.asarray(G, dtype=np.float64)
+    T_i, T_k, da = [], [], []
+    for t in cheb_states(L, lmax, p, R):
+        T_i.append(t[ri].copy())
+        T_k.append(t[ck].copy())
+        da.append(float(np.sum(G * t)))
+    if p == 0:
+        return np.zeros(len(entries)), np.array(da)
+    m_off = np.zeros(len(entries))
+    m_diag = np.zeros(len(entries))
+    A_next2 = np.zeros_like(G)       # A_{j+2}
+    A_next = a[p] * G                # A_{j+1}, starting at A_p
+    for j in range(p - 1, -1, -1):
+        cj = 1.0 if j == 0 else 2.0
+        m_off += cj * np.sum(A_next[ri] * T_k[j], axis=1)
+        m_diag += cj * np.sum(A_next[ri] * T_i[j], axis=1)
+        if j >= 1:
+            A_j = a[j] * G + 2.0 * (LtT @ A_next) - A_next2
+            A_next2, A_next = A_next, A_j
+    return (2.0 / lmax) * (m_diag - m_off), np.array(da)

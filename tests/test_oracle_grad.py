@@ -86,3 +86,13 @@ def test_loss_grad_vs_finite_differences():
             Ym[i, r] -= h
             fd = (oracle.rownorm_loss_grad(Yp, T)[0] - oracle.rownorm_loss_grad(Ym, T)[0]) / (2 * h)
             assert G[i, r] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_sampled_adjoint_equals_full():
+    g, w, L, lam, chi, lmax, a, R, T = _setup(seed=4, n=30, p=12, r=3)
+    G = W.signals_f64(g.n, 3, 8)
+    dw, da = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w, lmax, a, R, G)
+    ent = np.array([0, 3, g.nnz - 1, g.nnz // 2])
+    dws, das = oracle.cheb_filter_adjoint_sampled(g.n, g.row_ptr, g.col_idx, w, lmax, a, R, G, ent)
+    np.testing.assert_allclose(dws, dw[ent], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(das, da, rtol=1e-13)
