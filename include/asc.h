@@ -274,7 +274,9 @@ asc_status asc_batch_destroy(void *plan);
  *               T_{j-1}, Y) so that the gathered block stays cached; bit 1:
  *               the lanes of a row load the next 8 column indices / weights
  *               with one coalesced request and broadcast them in the row
- *               group (fewer vector-memory requests per neighbour).
+ *               group (fewer vector-memory requests per neighbour); bit 2:
+ *               each XCD processes one contiguous band of rows (L2 locality
+ *               for graphs whose neighbours are close in index order).
  * asc_autotune_filter times every candidate on the caller's graph and signals
  * for probe_steps recurrence steps (Y and ws are scratch; needs ws of
  * asc_filter_workspace(n, r, sig, 1) bytes), records the fastest and returns

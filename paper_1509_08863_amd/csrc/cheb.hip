@@ -497,7 +497,7 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
     bestE.ms = 1e30f;
     asc_status st = ASC_OK;
     for (int rs = 2 * vn; rs <= 16 * vn && rs <= rcap; rs *= 2) {
-        for (unsigned var = 0; var < 4; ++var) {
+        for (unsigned var = 0; var < 8; ++var) {
             const Plan P = plan_for(rs, var, r, sig);
             const int grid = grid_for(n, P.lpr);
             const int64_t tot = n * P.rs;
@@ -575,7 +575,7 @@ extern "C" asc_status asc_tune_set(int64_t n, int64_t nnz, int64_t r, asc_dtype 
     if (sig != ASC_F32 && sig != ASC_BF16) return fail(ASC_ERR_INVALID, "asc_tune_set: dtype");
     if (slice_cols != 0 && !valid_rs(slice_cols, sig))
         return fail(ASC_ERR_INVALID, "asc_tune_set: slice_cols=%d not supported for this dtype", slice_cols);
-    if (variant < 0 || variant > 3) return fail(ASC_ERR_INVALID, "asc_tune_set: variant=%d", variant);
+    if (variant < 0 || variant > 7) return fail(ASC_ERR_INVALID, "asc_tune_set: variant=%d", variant);
     std::lock_guard<std::mutex> lk(tune_mutex());
     auto &t = tune_table();
     const TuneKey key{n, nnz, r, (int)sig};
@@ -631,7 +631,7 @@ extern "C" asc_status asc_tune_load(const char *path) {
         double ms;
         if (sscanf(line, " {\"n\": %lld, \"nnz\": %lld, \"r\": %lld, \"dtype\": %d, \"slice_cols\": %d, \"variant\": %d, \"ms\": %lf",
                    &n, &nnz, &r, &dt, &rs, &var, &ms) == 7) {
-            if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && var >= 0 && var <= 3) {
+            if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && var >= 0 && var <= 7) {
                 asc_tune_set(n, nnz, r, (asc_dtype)dt, rs, var);
             }
         }

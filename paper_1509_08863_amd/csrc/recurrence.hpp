@@ -293,10 +293,26 @@ __global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
     const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)A.coeffs[0] : 0.0f;
     double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
     const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
-        if (row >= A.n) continue;
-        step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
+    if ((VAR & 4u) != 0 && gridDim.x >= 8) {
+        // XCD-contiguous tiles: workgroups are dispatched round-robin over the
+        // 8 XCDs, so workgroup b runs on XCD b % 8; give XCD x the x-th
+        // contiguous eighth of the rows, so that each XCD's L2 serves one band
+        // of a locality-ordered graph.  (A permutation of the tile order only.)
+        const int64_t xcd = blockIdx.x % 8, loc = blockIdx.x / 8;
+        const int64_t nx = (gridDim.x - xcd + 7) / 8;  // workgroups on this XCD
+        const int64_t chunk = (ntiles + 7) / 8;
+        const int64_t t0 = xcd * chunk, t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+        for (int64_t tile = t0 + loc; tile < t1; tile += nx) {
+            const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
+            if (row >= A.n) continue;
+            step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
+        }
+    } else {
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
+            if (row >= A.n) continue;
+            step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
+        }
     }
     if (MODE & M_PART) {
         __shared__ double lds[3 * NT / 64];
@@ -480,10 +496,14 @@ hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t
 
 template <typename TS, int LPR>
 hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int grid, hipStream_t s) {
-    switch (var & 3u) {
+    switch (var & 7u) {
         case 1u: return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
         case 2u: return launch_step_v<TS, LPR, 2u>(mode, A, grid, s);
         case 3u: return launch_step_v<TS, LPR, 3u>(mode, A, grid, s);
+        case 4u: return launch_step_v<TS, LPR, 4u>(mode, A, grid, s);
+        case 5u: return launch_step_v<TS, LPR, 5u>(mode, A, grid, s);
+        case 6u: return launch_step_v<TS, LPR, 6u>(mode, A, grid, s);
+        case 7u: return launch_step_v<TS, LPR, 7u>(mode, A, grid, s);
         default: return launch_step_v<TS, LPR, 0u>(mode, A, grid, s);
     }
 }
