@@ -33,17 +33,19 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# Memory traffic of the step kernel (cheb_step<float, 8, 2u, 0u>: one 32-column
-# slice of the 1M-node SBM, weights stored), from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE runs (KiB per dispatch), scaled by the same counters on the plain
-# 2 GiB copy kernel (FETCH_SIZE reads 1 GiB for 2 GiB read -> x2.0; WRITE_SIZE
-# reads 2 GiB -> x1.0).  Valid only while the kernel source is the one measured
-# (sha1 of the step-kernel region of recurrence.hpp); otherwise reported null.
+# Memory traffic of one launch of the recurrence step with Y accumulation on
+# the 1M-node SBM (one 32-column float32 slice, weights stored), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), scaled by
+# the same counters on the plain 2 GiB copy kernel (FETCH_SIZE reads 1 GiB for
+# 2 GiB read -> x2.0; WRITE_SIZE reads 2 GiB -> x1.0).  Keyed by the launch
+# variant; valid only while the kernel source is the one measured (sha1 of the
+# step-kernel region of recurrence.hpp), otherwise reported null.
 STEP_TRAFFIC = {
-    "src_sha1": "284df45145f1feb636e2f69884a2ce76b9883381",
+    "src_sha1": "a95ff79e15b5097e0c749979a820bc8e22aa4025",
     "workload": "sbm_n1e6_k50dir_d30_r96_p150",
-    "fetch_kib_per_launch": 2233118.06, "write_kib_per_launch": 250000.0,
-    "fetch_scale": 2.0, "write_scale": 1.0, "launches_per_unit": 3,
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    # (slice_cols, variant) -> (FETCH_SIZE, WRITE_SIZE), average over 2664 dispatches
+    "kib_per_launch": {(32, 0): (2233034.81, 250000.0), (32, 4): (2223176.33, 250000.0)},
 }
 
 
@@ -55,12 +57,13 @@ def step_kernel_sha1():
     return hashlib.sha1(src[a:b].encode()).hexdigest()
 
 
-def step_traffic_bytes(workload, slice_cols, launches):
+def step_traffic_bytes(workload, slice_cols, variant):
+    """Counter bytes per launch of the tuned step kernel, or None."""
     t = STEP_TRAFFIC
-    if step_kernel_sha1() != t["src_sha1"] or workload != t["workload"] or slice_cols != 32 or launches != 3:
+    kib = t["kib_per_launch"].get((slice_cols, variant))
+    if kib is None or step_kernel_sha1() != t["src_sha1"] or workload != t["workload"]:
         return None
-    per_launch = 1024 * (t["fetch_kib_per_launch"] * t["fetch_scale"] + t["write_kib_per_launch"] * t["write_scale"])
-    return per_launch * t["launches_per_unit"]
+    return 1024 * (kib[0] * t["fetch_scale"] + kib[1] * t["write_scale"])
 
 
 def b_step(n, nnz, r, bt, weighted=True):
@@ -166,6 +169,17 @@ def extra_batch(dev):
             "gen_s": round(gen_s, 1)}
 
 
+def copy_bandwidth(dev, nbytes, reps):
+    """Plain 16-byte-vector copy of nbytes (read + write counted)."""
+    import torch
+    import paper_1509_08863_amd as asc
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = _time(lambda: asc.stream_copy(src, dst), reps)
+    del src, dst
+    return {"copy_bytes_per_launch": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,9 +191,12 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--no-bwd", action="store_true", help="skip the fwd+bwd timing")
+    ap.add_argument("--no-pattern", action="store_true", help="skip the pattern-only (w = NULL) filter timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tiling)")
     ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
     ap.add_argument("--copy-probe", action="store_true", help="only time the plain 2 GiB copy kernel and exit")
+    ap.add_argument("--tune", default=None, metavar="RS,VAR",
+                    help="fixed float32 launch configuration (slice columns, variant) instead of the autotuner")
     return ap.parse_args()
 
 
@@ -193,19 +210,7 @@ def main():
 
     dev = "cuda:0"
     if args.copy_probe:
-        nbytes = 2 << 30
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        asc.stream_copy(src, dst)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            asc.stream_copy(src, dst)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 10
-        print(json.dumps({"copy_bytes_per_launch": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}))
+        print(json.dumps(copy_bandwidth(dev, 2 << 30, 10)))
         return
     cfg = W.CONFIGS[args.config]
     seeds = W.config_seeds(args.config)
@@ -230,11 +235,16 @@ def main():
     Y = torch.empty(n, r, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     tuned = {}
-    if not args.no_tune:
+    if args.tune:
+        rs_, var_ = (int(x) for x in args.tune.split(","))
+        asc.tune_set(G, r, torch.float32, rs_, var_)
+        tuned["f32"] = (rs_, var_, float("nan"))
+    elif not args.no_tune:
         lm0 = asc.lmax_estimate(G, v0d, 60)
         tuned["f32"] = asc.autotune_filter(G, lm0, R, 2)
-        if not args.no_bf16:
-            tuned["bf16"] = asc.autotune_filter(G, lm0, Rb, 2)
+    if not args.no_tune and not args.no_bf16:
+        lm0 = asc.lmax_estimate(G, v0d, 60)
+        tuned["bf16"] = asc.autotune_filter(G, lm0, Rb, 2)
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     comp_names = ["prepare", "lmax", "lambda_k_coeffs_filter", "-", "-", "normalize", "kmeans"]
@@ -298,6 +308,13 @@ def main():
 
     ms_f32 = time_filter(R)
     ms_bf16 = None if args.no_bf16 else time_filter(Rb)
+    # pattern-only graph (w = NULL: unit weights, no weight stream), same plan
+    ms_pat = None
+    if not args.no_pattern:
+        G_pat = asc.graph_prepare(rp, ci, None)
+        a_pat = asc.cheb_coeffs(out[1], out[0], p)
+        ms_pat = _time(lambda: asc.cheb_filter(G_pat, out[0], a_pat, R, Y), 3)
+        del G_pat
 
     # forward + backward: filter with checkpoints, row-normalised loss against
     # a fixed unit-row target, adjoint (edge-weight and coefficient gradients)
@@ -324,6 +341,7 @@ def main():
         ms_fb = e0.elapsed_time(e1) / reps
     bs32 = b_step(n, nnz, r, 4)
     bs16 = b_step(n, nnz, r, 2)
+    bs_pat = b_step(n, nnz, r, 4, weighted=False)
     gbs32 = p * bs32 / (ms_f32 * 1e-3) / 1e9
     gbs16 = None if ms_bf16 is None else p * bs16 / (ms_bf16 * 1e-3) / 1e9
 
@@ -361,7 +379,18 @@ def main():
                    "sample": f"FP64 C/OpenMP recurrence on {cols} of {r} columns, full graph, p={p}, "
                              f"{cpu_s:.1f} s; scaled by {r}/{cols} to one filter"}
 
-    steps_per_filter = p
+    # per-launch roofline of the step kernel: one launch = one recurrence step
+    # over one slice of rs columns; the algorithmic bytes of a step are shared
+    # out over its slices (the CSR stream counts once per step).  The filter's
+    # other kernels (diagonal, panel packing) take < 0.2% of its time.
+    rs32, var32 = tuned.get("f32", (32, 0))[:2]
+    nsl = -(-r // rs32)
+    launches = p * nsl
+    launch_ms = ms_f32 / launches
+    alg_launch = bs32 / nsl
+    traffic = step_traffic_bytes(cfg["name"], rs32, var32)
+    copy_big = copy_bandwidth(dev, 2 << 30, 10)
+    copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
         extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev)}
@@ -388,10 +417,19 @@ def main():
         "components_ms": {k_: round(v, 4) for k_, v in comp.items()},
         "lambda_max": lmax_h,
         "lambda_k_est": lam_k_h,
-        "roofline": {"bound": "hbm", "achieved": round(gbs32, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs32 / HBM_PEAK_GBS, 4),
-                     "traffic": step_traffic_bytes(cfg["name"], tuned.get("f32", (32,))[0], -(-r // 32)),
-                     "kernel": "cheb_step", "unit_bytes": bs32, "units_per_filter": steps_per_filter},
+        "pattern_only": None if ms_pat is None else {
+            "ms_per_filter_fwd": round(ms_pat, 4), "gbs": round(p * bs_pat / (ms_pat * 1e-3) / 1e9, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(alg_launch / (launch_ms * 1e-3) / 1e9, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg_launch / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": "cheb_step", "slice_cols": rs32, "variant": var32,
+                     "algorithmic_bytes_per_launch": round(alg_launch), "launch_ms": round(launch_ms, 5),
+                     "launches_per_filter": launches,
+                     "amplification": None if traffic is None else round(traffic / alg_launch, 3),
+                     "traffic_gbs": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 1),
+                     "copy_gbs_2GiB": round(copy_big["GBps"], 1), "copy_gbs_64MiB": round(copy_llc["GBps"], 1),
+                     "frac_of_copy": round(alg_launch / (launch_ms * 1e-3) / 1e9 / (copy_big["GBps"]), 4)},
         "cpu_baseline": cpu,
         "extra": extra,
         "gen_s": round(gen_s, 1),
