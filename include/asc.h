@@ -125,8 +125,9 @@ asc_status asc_cheb_coeffs(const double *lambda_c, int n_cut, const double *lmax
  *   ckpt_stride >= 2: the pairs (T_sc R, T_sc+1 R), sc = 0, c, 2c, ... < p;
  *   ckpt_stride == 1: every state T_0 R .. T_p R (the recurrence writes its
  *     states into this store instead of reusing two buffers; no recompute in
- *     the backward).  Its layout follows the tuning entry of (g, r, sig),
- *     which must not change before the matching backward call.
+ *     the backward).  Its size and panel layout use the default slice width
+ *     of (r, sig), independent of the tuning table, so a store sized by
+ *     asc_ckpt_bytes stays valid across asc_tune_set / asc_autotune_filter.
  * The call also computes |T_0|_F and |T_p|_F and raises ASC_FLAG_GROWTH /
  * ASC_FLAG_NONFINITE in the workspace flags (asc_read_flags). */
 size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int p);
@@ -222,7 +223,8 @@ asc_status asc_rownorm_loss_bwd(const float *Y, int64_t ldy, const float *target
 
 /* Adjoint of asc_cheb_filter: given G = dloss/dY (n x r float32, ldg) and the
  * checkpoints that asc_cheb_filter wrote with the same ckpt_stride (and the
- * same R, coeffs, lmax and tuning; ckpt_stride = 1: the full state store, also
+ * same R, coeffs and lmax; the checkpoint layouts do not depend on tuning;
+ * ckpt_stride = 1: the full state store, also
  * the one of asc_lambda_k_filter), computes
  *   dW[nnz]     = dloss/dw_e per stored entry (float32; NULL to skip),
  *   dcoeffs[p+1] = <G, T_j R>_F (float64; NULL to skip)

@@ -56,7 +56,8 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
                       void *ws, bool clear_flags, hipStream_t s) {
     const int64_t n = g->n;
     FilterWs F;
-    const Plan P = make_plan(g, r, sig);
+    const bool store_all = ckpt && ckpt_stride == 1;
+    const Plan P = store_all ? store_plan(g, r, sig) : make_plan(g, r, sig);
     filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 2, 1, ws, &F);
     uint32_t *flags = &F.hdr->flags;
     diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, flags,
@@ -76,7 +77,6 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
     // ckpt_stride >= 2: (T_sc, T_sc+1) pairs, row-major blocks; ckpt_stride == 1:
     // every state in panel layout [slice][j][n x rs] (the recurrence writes its
     // states straight into their slots, nothing is overwritten)
-    const bool store_all = ckpt && ckpt_stride == 1;
     const size_t ckb = (ckpt && !store_all) ? ck_block_bytes(n, r, sig) : 0;
     auto ck_block = [&](int seg, int which) -> void * {
         return static_cast<char *>(ckpt) + ((size_t)seg * 2 + which) * ckb;
@@ -336,7 +336,7 @@ extern "C" size_t asc_filter_workspace(int64_t n, int64_t r, asc_dtype sig, int 
 extern "C" size_t asc_ckpt_bytes(const asc_graph *g, int64_t r, asc_dtype sig, int p, int ckpt_stride) {
     if (!g || g->n < 1 || r < 1 || p < 0 || ckpt_stride < 1 || (sig != ASC_F32 && sig != ASC_BF16)) return 0;
     if (ckpt_stride == 1) {
-        const Plan P = make_plan(g, r, sig);
+        const Plan P = store_plan(g, r, sig);
         return (size_t)P.nslices * (p + 1) * panel_bytes(g->n, P.rs, sig);
     }
     return (size_t)nseg_of(p, ckpt_stride) * 2 * ck_block_bytes(g->n, r, sig);
@@ -731,7 +731,7 @@ extern "C" asc_status asc_lambda_k_filter(const asc_graph *g, const double *lmax
     double *mu, *co;
     lkf_ws_layout(n, r, sig, p, ws, &mws, &mu, &co);
     if (coeffs_out) co = coeffs_out;
-    const Plan P = make_plan(g, r, sig);
+    const Plan P = store_plan(g, r, sig);
     const int msteps = std::max(1, (p + 1) / 2);
     FilterWs F;
     filter_ws_layout(n, rs_for_ws(r, sig), (int)((r + 2 * vn_of(sig) - 1) / (2 * vn_of(sig))), sig, msteps, msteps,

@@ -495,7 +495,7 @@ extern "C" asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax
         transpose_map_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->row_ptr, g->col_idx, B.tr, flags);
         ASC_LAUNCHED();
     }
-    const Plan P = make_plan(g, r, sig);
+    const Plan P = store_all ? store_plan(g, r, sig) : make_plan(g, r, sig);
     const int grid = grid_for(n, P.lpr);
     const size_t pb = (size_t)n * P.rs * esize(sig);
     auto panel = [&](int q) -> void * { return static_cast<char *>(B.panels) + (size_t)q * pb; };

@@ -471,6 +471,16 @@ Plan make_plan(const asc_graph *g, int64_t r, asc_dtype dt) {
     return plan_for(default_rs(r, dt), 0u, r, dt);
 }
 
+// The state store (every T_j kept, panel layout [slice][j][n x rs]) always
+// uses the default slice width for (r, dtype), whatever the tuning says, so its
+// size and layout cannot change between sizing, the forward pass that writes it
+// and the backward pass that reads it; the tuned variant bits still apply.
+Plan store_plan(const asc_graph *g, int64_t r, asc_dtype dt) {
+    TuneEntry e;
+    const unsigned var = tuned(g->n, g->nnz, r, dt, &e) ? (unsigned)e.var : 0u;
+    return plan_for(default_rs(r, dt), var, r, dt);
+}
+
 int grid_for(int64_t n, int lpr) {
     const int64_t rows = (64 / lpr) * (NT / 64);
     int64_t b = (n + rows - 1) / rows;

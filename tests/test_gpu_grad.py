@@ -152,3 +152,38 @@ def test_state_store_forward_and_backward_equal_checkpoint_path(r, p):
     dw_ref, da_ref = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w32, lmax, a, R64, G64)
     assert rel_fro(d1[0], dw_ref) <= TOL_DW
     assert rel_fro(d1[1], da_ref) <= TOL_DA
+
+
+def test_state_store_layout_is_independent_of_tuning():
+    # r = 72: the default 32-column slices give 96 stored columns, 64-column
+    # slices would need 128; a store sized before a re-tune must stay valid
+    r, p = 72, 12
+    g, w64, L, lmax, a, Rs, R64, T = _problem(n=1500, r=r, p=p)
+    Gd = upload_graph(g, w=w64.astype(np.float32))
+    G64 = W.signals_f64(g.n, r, 5).astype(np.float32).astype(np.float64)
+    Rd = block_f32(Rs)
+    lib = asc._abi.lib()
+    nb = lib.asc_ckpt_bytes(Gd.c(), r, asc.ASC_F32, p, 1)
+    states = asc.workspace(nb, DEV)
+    Y0, _ = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=1, ckpt=states)
+    d0 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, states, 1, block_f32(G64))]
+    Y0 = host(Y0)
+    try:
+        asc.tune_set(Gd, r, torch.float32, 64, 4)
+        assert lib.asc_ckpt_bytes(Gd.c(), r, asc.ASC_F32, p, 1) == nb
+        Y1, ck = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=1, ckpt=states)
+        assert ck.data_ptr() == states.data_ptr()
+        asc.tune_set(Gd, r, torch.float32, 16, 2)  # re-tuned between forward and backward
+        d1 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, states, 1, block_f32(G64))]
+        _, lam, _, _, _ = asc.lambda_k_filter(Gd, scalar(lmax), 5, p, 8, Rd, None, states)
+        assert 0.0 < host(lam)[0] <= lmax
+    finally:
+        asc.tune_set(Gd, r, torch.float32, 0, 0)
+    # the variant bits change only the tile schedule: results are bit-identical
+    np.testing.assert_array_equal(host(Y1), Y0)
+    np.testing.assert_array_equal(d1[0], d0[0])
+    np.testing.assert_array_equal(d1[1], d0[1])
+    w32 = w64.astype(np.float32).astype(np.float64)
+    dw_ref, da_ref = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w32, lmax, a, R64, G64)
+    assert rel_fro(d1[0], dw_ref) <= TOL_DW
+    assert rel_fro(d1[1], da_ref) <= TOL_DA
