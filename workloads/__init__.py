@@ -198,6 +198,75 @@ def gmm_knn(n: int, d: int, k: int, knn: int, seed: int) -> Graph:
     return Graph(n=n, row_ptr=rp, col_idx=ci, w=None, d2=d2s.astype(np.float32), labels=z, k=k)
 
 
+def gmm2d_points(n: int, k: int, seed: int):
+    """Planar mixture of k Gaussians with different means and spreads:
+    mu_c uniform in [0, 20]^2, sigma_c uniform in [0.3, 1.2], z_i uniform;
+    x_i = mu_{z_i} + sigma_{z_i} N(0, I_2)."""
+    rng = rng_for(seed)
+    mu = rng.uniform(0.0, 20.0, size=(k, 2))
+    sd = rng.uniform(0.3, 1.2, size=k)
+    z = rng.integers(0, k, size=n)
+    x = mu[z] + sd[z, None] * rng.standard_normal((n, 2))
+    return x, z.astype(np.int32)
+
+
+def knn_graph(x: np.ndarray, knn: int) -> Graph:
+    """Union-symmetrised knn-nearest-neighbour pattern of the rows of x
+    (self excluded), unit weights, squared edge lengths in ``d2``."""
+    from scipy.spatial import cKDTree
+    n = x.shape[0]
+    _, nb = cKDTree(x).query(x, k=knn + 1, workers=-1)
+    src = np.repeat(np.arange(n, dtype=np.int64), knn + 1)
+    dst = nb.reshape(-1).astype(np.int64)
+    keep = dst != src
+    a = np.minimum(src[keep], dst[keep])
+    b = np.maximum(src[keep], dst[keep])
+    key = np.unique(a * n + b)
+    u, v = key // n, key % n
+    g = from_edges(n, np.stack([u, v], 1))
+    # squared lengths per stored entry (row order of the CSR)
+    rows = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    g.d2 = np.sum((x[rows] - x[g.col_idx]) ** 2, axis=1).astype(np.float32)
+    return g
+
+
+def gmm2d_knn(n: int, k: int, seed: int, knn: int | None = None) -> Graph:
+    """The planar mixture's kNN graph with knn = round(ln n) by default
+    (K ~ log N); ``labels`` holds the generating component."""
+    x, z = gmm2d_points(n, k, seed)
+    g = knn_graph(x, int(round(np.log(n))) if knn is None else knn)
+    g.labels = z
+    g.k = k
+    return g
+
+
+def unit_signals(n: int, r: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Unit-variance Gaussian columns drawn in float64: (float32, as float64)."""
+    f32 = rng_for(seed).standard_normal((n, r)).astype(np.float32)
+    return f32, f32.astype(np.float64)
+
+
+def stability_pools(n: int, J: int, eta_max: int, seed: int):
+    """J realisations of eta_max unit-variance columns, side by side: an
+    n x (J * eta_max) float32 block (realisation j = columns j*eta_max ...)."""
+    return unit_signals(n, J * eta_max, seed)
+
+
+def stability_init_rows(n: int, ks, J: int, reps: int, seed: int) -> np.ndarray:
+    """Initial k-means rows for every (k, realisation, replicate): int32
+    [len(ks)][J][reps][max(ks)] (the first k entries are used; the rest repeat
+    the first row)."""
+    kmax = max(ks)
+    out = np.zeros((len(ks), J, reps, kmax), dtype=np.int32)
+    for q, k in enumerate(ks):
+        for j in range(J):
+            for t in range(reps):
+                rows = init_rows(n, k, seed + 100_000 * q + 1000 * j + t)
+                out[q, j, t, :k] = rows
+                out[q, j, t, k:] = rows[0]
+    return out
+
+
 def bf16_round(x: np.ndarray) -> np.ndarray:
     """Round float32 values to the nearest bfloat16 (ties to even); returns the
     bfloat16 bit patterns as uint16."""
@@ -280,7 +349,25 @@ CONFIGS = {
     3: dict(name="sbm_n1e6_k50dir_d30_r96_p150", n=1_000_000, k=50, r=96, p=150, steps=12, kmeans_iters=10),
     4: dict(name="batch64_sbm_r48_p80_t8", r=48, p=80, trials=8, n_graphs=64),
     5: dict(name="gmm_knn10_n2e5_d16_k20_r64_p100", n=200_000, k=20, r=64, p=100, sigma=2.0, steps=12),
+    # stability measure gamma(k): planar 10-Gaussian mixture, kNN with K = round(ln N),
+    # k = 2..20, eta_k = 2k, J = 20 realisations
+    6: dict(name="stab_gmm2d_n5000_k10_knn9_J20_k2to20_rep20", n=5000, k_true=10, ks=list(range(2, 21)), J=20,
+            reps=20, p=150, steps=12, kmeans_iters=20),
+    7: dict(name="stab_gmm2d_n1e5_k20_knn12_J20_k10to30_rep4", n=100_000, k_true=20, ks=list(range(10, 31)), J=20,
+            reps=4, p=150, steps=12, kmeans_iters=20),
 }
+
+
+def stability_config(c: int):
+    """(graph, ks, etas, J, pools (float32, float64), init rows) of a stability configuration."""
+    cfg = CONFIGS[c]
+    s = config_seeds(c)
+    g = gmm2d_knn(cfg["n"], cfg["k_true"], s["graph"])
+    ks = cfg["ks"]
+    etas = [2 * k for k in ks]
+    pools = stability_pools(g.n, cfg["J"], max(etas), s["signals"])
+    rows = stability_init_rows(g.n, ks, cfg["J"], cfg["reps"], s["kmeans"])
+    return g, ks, etas, cfg["J"], pools, rows
 
 
 def batch_specs(seed: int = BASE_SEED + 40, n_graphs: int = 64):
