@@ -67,6 +67,7 @@ typedef enum { ASC_F32 = 0, ASC_BF16 = 1 } asc_dtype;
 #define ASC_FLAG_NONFINITE 1u
 #define ASC_FLAG_GROWTH 2u      /* |T_j R|_F > 1.5 |R|_F: lambda_max too small */
 #define ASC_FLAG_BAD_GRAPH 4u
+#define ASC_FLAG_BAD_INPUT 8u   /* a cluster label outside [0, k) was skipped */
 
 /* Undirected weighted graph W (Sec. 2.1) in CSR, both (i,j) and (j,i) stored.
  * row_ptr[n+1] (row_ptr[0] = 0, row_ptr[n] = nnz < 2^31), col_idx[nnz]
@@ -264,6 +265,49 @@ asc_status asc_batch_info(const void *plan, int *slice_cols, int *tile_rows, int
 asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
                          double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph, void *stream);
 asc_status asc_batch_destroy(void *plan);
+
+/* Stability measure for the number of clusters (Sec. 4.3, Eq. stab): for every
+ * k = k_min..k_max the algorithm of Sec. 4.1 (steps 2-6) runs on J independent
+ * realisations of its random signals, and
+ *   gamma(k) = mean over the J(J-1)/2 pairs i < j of ARI(C_k^i, C_k^j),
+ * ARI being the adjusted Rand index of Hubert & Arabie (J. Classification
+ * 1985).  k* = argmax gamma is the estimated number of clusters.
+ * Realisation j for k uses the first eta_host[k - k_min] columns of its pool,
+ * columns [j*eta_max, (j+1)*eta_max) of R (n x J*eta_max, dtype sig, leading
+ * dim ldr, i.i.d. unit-variance entries; the method's variance 1/eta_k is
+ * applied inside).  Per (k, j): lambda_k by the dichotomy (`steps` steps) on
+ * the eigenvalue counts of its own signals, the order-p filter at that
+ * cut-off, row normalisation, and k-means (Lloyd, kmeans_iters iterations,
+ * then a final assignment) from each of `reps` replicates, whose initial
+ * centroids are the rows init_rows[k - k_min][j][rep][0..k-1] of the features
+ * (int32 [nk][J][reps][k_max], rows in [0, n)); the replicate of least inertia
+ * sum_i |f_i - mu_{label_i}|^2 (float64; lowest replicate on ties) gives C_k^j.
+ * One recurrence pass keeps every state of all J*eta_max columns (the state
+ * store is part of ws); the k-dependent work reads the store only.
+ * Outputs (device): gamma[nk]; optional (NULL to skip): ari[nk][J(J-1)/2]
+ * (pair order (0,1), (0,2), ..., (1,2), ...), labels[nk][J][n],
+ * lambda_k[nk][J], traj[nk][J][steps][2] (mid, count), inertia[nk][J][reps].
+ * Limits: 1 <= k_min <= k_max <= min(n, 128), at most 256 values of k;
+ * 2 <= J <= 1024; J*reps <= 65535; 1 <= eta <= eta_max, J*eta_max <= 65536;
+ * 1 <= p <= 8192.  asc_stability_workspace returns 0 for invalid arguments.
+ * ws flags (asc_read_flags): those of the recurrence pass. */
+size_t asc_stability_workspace(const asc_graph *g, int k_min, int k_max, const int *eta_host, int J, int reps, int p,
+                               int steps, asc_dtype sig, int64_t eta_max);
+asc_status asc_stability(const asc_graph *g, const double *lmax, int k_min, int k_max, const int *eta_host, int J,
+                         int reps, int p, int steps, int kmeans_iters, const void *R, asc_dtype sig, int64_t eta_max,
+                         int64_t ldr, const int32_t *init_rows, double *gamma, double *ari, int32_t *labels,
+                         double *lambda_k, double *traj, double *inertia, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjusted Rand index of every pair a < b of J labellings (Sec. 4.3, after
+ * Hubert & Arabie 1985): labels int32, row a at labels[a*ldl], n entries in
+ * [0, k) (an entry outside is skipped and raises ASC_FLAG_BAD_INPUT in ws),
+ * k <= 128, 2 <= J <= 1024.  ari[J(J-1)/2] in the order (0,1), (0,2), ...;
+ * mean (optional) = their mean.  The contingency counts and the pair sums are
+ * exact integers; ARI = 2(index C(n,2) - sa sb) / ((sa+sb) C(n,2) - 2 sa sb),
+ * 1 where that is 0/0 (both labellings one cluster, or both all singletons). */
+size_t asc_ari_workspace(void);
+asc_status asc_ari_pairs(const int32_t *labels, int64_t n, int64_t ldl, int J, int k, double *ari, double *mean,
+                         void *ws, size_t ws_bytes, void *stream);
 
 /* Kernel configuration of the recurrence step, kept in a process-wide table
  * keyed by (n, nnz, r, sig); calls on a graph without an entry use the

@@ -353,6 +353,56 @@ class Batch:
             pass
 
 
+def stability(g: Graph, lmax: torch.Tensor, k_min: int, k_max: int, etas, J: int, reps: int, p: int, steps: int,
+              kmeans_iters: int, R: torch.Tensor, eta_max: int, init_rows: torch.Tensor, ws: torch.Tensor | None = None):
+    """Stability measure gamma(k), k = k_min..k_max (Eq. stab).  R is n x (J *
+    eta_max) unit-variance columns (realisation j = columns j*eta_max ...);
+    init_rows int32 [nk][J][reps][k_max].  Returns a dict of device tensors:
+    gamma [nk], ari [nk][J(J-1)/2], labels [nk][J][n], lambda_k [nk][J],
+    traj [nk][J][steps][2], inertia [nk][J][reps]."""
+    L = _abi.lib()
+    n = R.shape[0]
+    nk = k_max - k_min + 1
+    eta_arr = (ctypes.c_int * nk)(*[int(e) for e in etas])
+    dt = _dtype_code(R)
+    need = L.asc_stability_workspace(g.c(), k_min, k_max, eta_arr, J, reps, p, steps, dt, eta_max)
+    if need == 0:
+        raise _abi.AscError(_abi.ASC_ERR_INVALID, L.asc_last_error().decode())
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, R.device)
+    dev = R.device
+    npairs = J * (J - 1) // 2
+    out = {
+        "gamma": torch.empty(nk, dtype=torch.float64, device=dev),
+        "ari": torch.empty(nk, npairs, dtype=torch.float64, device=dev),
+        "labels": torch.empty(nk, J, n, dtype=torch.int32, device=dev),
+        "lambda_k": torch.empty(nk, J, dtype=torch.float64, device=dev),
+        "traj": torch.empty(nk, J, max(steps, 1), 2, dtype=torch.float64, device=dev),
+        "inertia": torch.empty(nk, J, reps, dtype=torch.float64, device=dev),
+    }
+    _abi.check(L.asc_stability(g.c(), _ptr(lmax), k_min, k_max, eta_arr, J, reps, p, steps, kmeans_iters, _ptr(R), dt,
+                               eta_max, _ld(R), _ptr(init_rows), _ptr(out["gamma"]), _ptr(out["ari"]),
+                               _ptr(out["labels"]), _ptr(out["lambda_k"]), _ptr(out["traj"]), _ptr(out["inertia"]),
+                               _ptr(ws), ws.numel(), _stream()))
+    out["traj"] = out["traj"][:, :, :steps]
+    stability.last_ws = ws
+    return out
+
+
+def ari_pairs(labels: torch.Tensor, k: int):
+    """Adjusted Rand index of every pair (a, b), a < b, of the J labellings in
+    the rows of labels (int32 J x n, values in [0, k)); returns (ari, mean)."""
+    L = _abi.lib()
+    J, n = labels.shape
+    ari = torch.empty(J * (J - 1) // 2, dtype=torch.float64, device=labels.device)
+    mean = torch.empty(1, dtype=torch.float64, device=labels.device)
+    ws = workspace(L.asc_ari_workspace(), labels.device)
+    _abi.check(L.asc_ari_pairs(_ptr(labels), n, labels.stride(0), J, k, _ptr(ari), _ptr(mean), _ptr(ws), ws.numel(),
+                               _stream()))
+    ari_pairs.last_ws = ws
+    return ari, mean
+
+
 def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     """dst <- src (same byte size), plain 16-byte streaming copy kernel."""
     nb = src.numel() * src.element_size()

@@ -18,6 +18,8 @@ ASC_F32 = 0
 ASC_BF16 = 1
 ASC_FLAG_NONFINITE = 1
 ASC_FLAG_GROWTH = 2
+ASC_FLAG_BAD_GRAPH = 4
+ASC_FLAG_BAD_INPUT = 8
 
 STATUS_NAMES = {0: "ASC_OK", 1: "ASC_ERR_INVALID", 2: "ASC_ERR_WORKSPACE", 3: "ASC_ERR_HIP",
                 4: "ASC_ERR_NONFINITE", 5: "ASC_ERR_LMAX_TOO_SMALL"}
@@ -80,6 +82,11 @@ SIGNATURES = {
                              ctypes.POINTER(ctypes.c_int)]),
     "asc_batch_run": (I32, [P, P, P, I64, P, I64, P, P, P, SZ, I32, P]),
     "asc_batch_destroy": (I32, [P]),
+    "asc_stability_workspace": (SZ, [GP, I32, I32, P, I32, I32, I32, I32, I32, I64]),
+    "asc_stability": (I32, [GP, P, I32, I32, P, I32, I32, I32, I32, I32, P, I32, I64, I64, P, P, P, P, P, P, P, P,
+                            SZ, P]),
+    "asc_ari_workspace": (SZ, []),
+    "asc_ari_pairs": (I32, [P, I64, I64, I32, I32, P, P, P, SZ, P]),
     "asc_tune_set": (I32, [I64, I64, I64, I32, I32, I32]),
     "asc_tune_get": (I32, [I64, I64, I64, I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "asc_tune_save": (I32, [ctypes.c_char_p]),

@@ -13,6 +13,7 @@
 // coefficients, so no value returns to the host.  The whole sequence is
 // captured once into a HIP graph and replayed as a single launch.
 #include "recurrence.hpp"
+#include "coeffs.hpp"
 
 #include <vector>
 
@@ -108,15 +109,6 @@ __global__ void batch_diag_kernel(const Tile *__restrict__ tiles, int ntiles, co
     }
 }
 
-__device__ double coeff_dev(double lc, double L, int p, int j) {
-    double xc = 2.0 * lc / L - 1.0;
-    xc = fmin(fmax(xc, -1.0), 1.0);
-    const double th = acos(xc);
-    double c = (j == 0) ? 1.0 - th / kPi : -2.0 * sin(j * th) / (j * kPi);
-    const double a = kPi / (p + 2);
-    return c * (((p + 2 - j) * cos(j * a) + sin(j * a) / tan(a)) / (p + 2));
-}
-
 // one block per graph: moments from the tile partials (doubling identities),
 // dichotomy on [0, lmax_g], coefficients of the final filter
 __global__ __launch_bounds__(NT) void batch_dichotomy_kernel(
@@ -159,7 +151,7 @@ __global__ __launch_bounds__(NT) void batch_dichotomy_kernel(
     for (int s = 0; s < steps; ++s) {
         const double mid = 0.5 * (lo + hi);
         double v[1] = {0.0};
-        for (int j = threadIdx.x; j <= p; j += NT) v[0] += coeff_dev(mid, L, p, j) * mu[j];
+        for (int j = threadIdx.x; j <= p; j += NT) v[0] += cheb_coeff_dev(mid, L, p, j, 1) * mu[j];
         block_sum<1, NT>(v, lds);
         if (threadIdx.x == 0) {
             bc = v[0];
@@ -173,7 +165,7 @@ __global__ __launch_bounds__(NT) void batch_dichotomy_kernel(
         __syncthreads();
     }
     if (threadIdx.x == 0) lambda_k[g] = hi;
-    for (int j = threadIdx.x; j <= p; j += NT) coeffs[(int64_t)g * (p + 1) + j] = coeff_dev(hi, L, p, j);
+    for (int j = threadIdx.x; j <= p; j += NT) coeffs[(int64_t)g * (p + 1) + j] = cheb_coeff_dev(hi, L, p, j, 1);
 }
 
 struct BatchPlan {

@@ -20,6 +20,8 @@
 // 16*LPR-byte segment per neighbour.  Optional float64 partial sums per block
 // (|T_j|^2, <T_{j+1}, T_j>, |T_{j+1}|^2) feed the moments and the growth check.
 #include "recurrence.hpp"
+#include "coeffs.hpp"
+#include "store.hpp"
 
 #include <cmath>
 #include <mutex>
@@ -212,19 +214,6 @@ size_t filter_ws(int64_t n, int64_t r, asc_dtype sig) {
 // ---------------------------------------------------------------------------
 // coefficients and the dichotomy (float64 on the device)
 // ---------------------------------------------------------------------------
-__device__ double cheb_coeff_dev(double lc, double L, int p, int j, int jackson) {
-    double xc = 2.0 * lc / L - 1.0;
-    xc = fmin(fmax(xc, -1.0), 1.0);
-    const double th = acos(xc);
-    double c = (j == 0) ? 1.0 - th / kPi : -2.0 * sin(j * th) / (j * kPi);
-    if (jackson) {
-        const double a = kPi / (p + 2);
-        const double g = ((p + 2 - j) * cos(j * a) + sin(j * a) / tan(a)) / (p + 2);
-        c *= g;
-    }
-    return c;
-}
-
 namespace {
 
 __global__ void coeffs_kernel(const double *__restrict__ lc, int n_cut, const double *__restrict__ lmax, int p,
@@ -656,6 +645,61 @@ extern "C" asc_status asc_autotune_filter(const asc_graph *g, const double *lmax
     if (best_ms_per_step) *best_ms_per_step = e.ms;
     return ASC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// the state store for other translation units
+// ---------------------------------------------------------------------------
+namespace asc {
+
+StoreLayout store_layout(const asc_graph *g, int64_t r, asc_dtype sig) {
+    const Plan P = store_plan(g, r, sig);
+    return StoreLayout{P.rs, P.nslices, panel_bytes(g->n, P.rs, sig)};
+}
+
+size_t store_ws_bytes(int64_t n, int64_t r, asc_dtype sig) {
+    return filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 1, 1, nullptr, nullptr);
+}
+
+asc_status run_store(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig, int64_t r,
+                     int64_t ldr, void *states, void *ws, hipStream_t s) {
+    const int64_t n = g->n;
+    const Plan P = store_plan(g, r, sig);
+    FilterWs F;
+    filter_ws_layout(n, rs_for_ws(r, sig), 1, sig, 1, 1, ws, &F);
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, &F.hdr->flags, 1);
+    ASC_LAUNCHED();
+    const int grid = grid_for(n, P.lpr);
+    const size_t pbytes = panel_bytes(n, P.rs, sig);
+    auto slot = [&](int sl, int j) -> void * { return static_cast<char *>(states) + ((size_t)sl * (p + 1) + j) * pbytes; };
+    const int64_t tot = n * P.rs;
+    const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    for (int sl = 0; sl < P.nslices; ++sl) {
+        const int64_t c0 = (int64_t)sl * P.rs;
+        if (sig == ASC_F32)
+            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)slot(sl, 0));
+        else
+            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)slot(sl, 0));
+        ASC_LAUNCHED();
+        StepArgs A{};
+        A.n = n;
+        A.rp = g->row_ptr;
+        A.ci = g->col_idx;
+        A.w = g->w;
+        A.diag = F.diag;
+        A.beta = F.beta;
+        for (int j = 0; j < p; ++j) {
+            A.cur = slot(sl, j);
+            A.prev = j == 0 ? nullptr : slot(sl, j - 1);
+            A.out = slot(sl, j + 1);
+            A.j = j;
+            hipError_t e = launch_step(sig, P.lpr, P.var, j == 0 ? M_FIRST : 0u, A, grid, s);
+            if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    return ASC_OK;
+}
+
+}  // namespace asc
 
 // ---------------------------------------------------------------------------
 // one-pass lambda_k + filter: states are kept, Y is formed at the end

@@ -2,6 +2,7 @@
 // signals (footnote of Sec. 2.1) and k-means with the Euclidean distance
 // (Sec. 2.2 step 4; step 6 of the algorithm in Sec. 4.1).
 #include "common.hpp"
+#include "cluster.hpp"
 
 #include <algorithm>
 
@@ -9,6 +10,19 @@ namespace asc {
 namespace {
 
 constexpr int NT = 256;
+
+// Several independent problems in one launch: problem b = blockIdx.y reads
+// feature block b / fdiv (replicates of one realisation share their features)
+// and owns centroid block b, label block b and init-row block b.
+struct Bat {
+    int64_t f;       // elements between feature blocks
+    int fdiv;        // problems per feature block
+    int64_t c;       // elements between centroid blocks
+    int64_t l;       // elements between label / distance blocks
+    int64_t rows;    // elements between init-row blocks
+};
+constexpr Bat kOne{0, 1, 0, 0, 0};
+__device__ __forceinline__ int64_t fblk(const Bat &b) { return (int64_t)(blockIdx.y / b.fdiv) * b.f; }
 
 // one wavefront per row: |y_i| accumulated in float64, y_i /= |y_i|
 __global__ __launch_bounds__(NT) void normalize_kernel(float *__restrict__ Y, int64_t n, int64_t r, int64_t ldy,
@@ -33,7 +47,10 @@ __global__ __launch_bounds__(NT) void normalize_kernel(float *__restrict__ Y, in
 }
 
 __global__ void init_rows_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
-                                 const int32_t *__restrict__ rows, int k, float *__restrict__ C) {
+                                 const int32_t *__restrict__ rows, int k, float *__restrict__ C, Bat bt) {
+    F += fblk(bt);
+    rows += blockIdx.y * bt.rows;
+    C += blockIdx.y * bt.c;
     const int64_t total = (int64_t)k * r;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(q / r);
@@ -58,9 +75,15 @@ __device__ __forceinline__ void better(double &d, int &c, double d2, int c2) {
 
 __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                                     const float *__restrict__ Cg, int k, int use_lds,
-                                                    int32_t *__restrict__ labels, float *__restrict__ dist2) {
+                                                    int32_t *__restrict__ labels, float *__restrict__ dist2,
+                                                    double *__restrict__ dist64, Bat bt) {
 #pragma clang fp contract(off)
     extern __shared__ float Ct[];
+    F += fblk(bt);
+    Cg += blockIdx.y * bt.c;
+    labels += blockIdx.y * bt.l;
+    if (dist2) dist2 += blockIdx.y * bt.l;
+    if (dist64) dist64 += blockIdx.y * bt.l;
     const int kp = (k + 63) & ~63;
     if (use_lds) {
         for (int64_t q = threadIdx.x; q < (int64_t)kp * r; q += NT) {
@@ -115,6 +138,7 @@ __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F,
         if (lane == 0) {
             labels[iu] = bc;
             if (dist2) dist2[iu] = (float)best;
+            if (dist64) dist64[iu] = best;
         }
     }
 }
@@ -123,9 +147,13 @@ __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F,
 // order (deterministic), partial [block][k][r] and counts [block][k]
 __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                       const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
-                                      double *__restrict__ part, int64_t *__restrict__ pcount) {
+                                      double *__restrict__ part, int64_t *__restrict__ pcount, Bat bt) {
     extern __shared__ double S[];  // k*r sums then k counts (as double)
     const int64_t kr = (int64_t)k * r;
+    F += fblk(bt);
+    labels += blockIdx.y * bt.l;
+    part += (int64_t)blockIdx.y * gridDim.x * kr;
+    pcount += (int64_t)blockIdx.y * gridDim.x * k;
     for (int64_t q = threadIdx.x; q < kr + k; q += blockDim.x) S[q] = 0.0;
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
@@ -160,8 +188,12 @@ __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, in
 // same, for k*r too large for LDS: sums kept in the partial array itself
 __global__ void update_partial_global_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                              const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
-                                             double *__restrict__ part, int64_t *__restrict__ pcount) {
+                                             double *__restrict__ part, int64_t *__restrict__ pcount, Bat bt) {
     const int64_t kr = (int64_t)k * r;
+    F += fblk(bt);
+    labels += blockIdx.y * bt.l;
+    part += (int64_t)blockIdx.y * gridDim.x * kr;
+    pcount += (int64_t)blockIdx.y * gridDim.x * k;
     double *S = part + (int64_t)blockIdx.x * kr;
     for (int64_t q = threadIdx.x; q < kr; q += blockDim.x) S[q] = 0.0;
     int64_t *cnt = pcount + (int64_t)blockIdx.x * k;
@@ -182,9 +214,13 @@ __global__ void update_partial_global_kernel(const float *__restrict__ F, int64_
 // fixed butterfly adds the 64 lane sums (deterministic).
 __global__ void update_final_kernel(int nblocks, int64_t r, int k, const double *__restrict__ part,
                                     const int64_t *__restrict__ pcount, float *__restrict__ C,
-                                    int64_t *__restrict__ counts) {
+                                    int64_t *__restrict__ counts, Bat bt) {
     const int lane = threadIdx.x & 63;
     const int64_t kr = (int64_t)k * r;
+    part += (int64_t)blockIdx.y * nblocks * kr;
+    pcount += (int64_t)blockIdx.y * nblocks * k;
+    C += blockIdx.y * bt.c;
+    if (counts) counts += (int64_t)blockIdx.y * k;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t q = w0; q < kr; q += nw) {
@@ -215,6 +251,69 @@ asc_status check_feat(const float *F, int64_t n, int64_t r, int64_t ldf, const c
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers shared by the public entry points and the batched callers
+// ---------------------------------------------------------------------------
+static Bat to_bat(const KmBatch &b) { return Bat{b.fstride, b.fdiv, b.cstride, b.lstride, b.rows_stride}; }
+
+int km_update_blocks(int64_t n, int count) {
+    if (count <= 1) return update_blocks(n);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(update_blocks(n), 16384 / count));
+}
+
+void km_normalize(float *Y, int64_t n, int64_t r, int64_t ldy, float *norms, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>((n * 64 + NT - 1) / NT, 16384);
+    normalize_kernel<<<grid, NT, 0, s>>>(Y, n, r, ldy, norms);
+}
+
+void km_init_rows(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *rows, int k, float *C,
+                  const KmBatch &b, hipStream_t s) {
+    const int64_t total = (int64_t)k * r;
+    const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 1024), (unsigned)b.count);
+    init_rows_kernel<<<grid, 256, 0, s>>>(F, n, r, ldf, rows, k, C, to_bat(b));
+}
+
+void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
+               float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
+    const size_t cbytes = (size_t)((k + 63) & ~63) * r * sizeof(float);
+    const int use_lds = cbytes <= 64 * 1024;
+    const int64_t want = (n * 64 + NT - 1) / NT;
+    const int64_t cap = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
+    assign_kernel<<<grid, NT, use_lds ? cbytes : 0, s>>>(F, n, r, ldf, C, k, use_lds, labels, dist2, dist64,
+                                                         to_bat(b));
+}
+
+size_t km_update_ws(int64_t n, int64_t r, int k, int count) {
+    Arena a(nullptr);
+    const int nb = km_update_blocks(n, count);
+    a.take<double>((size_t)count * nb * k * r);
+    a.take<int64_t>((size_t)count * nb * k);
+    return a.size();
+}
+
+void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k, float *C,
+               int64_t *counts, void *ws, const KmBatch &b, hipStream_t s) {
+    Arena a(ws);
+    const int nb = km_update_blocks(n, b.count);
+    double *part = a.take<double>((size_t)b.count * nb * k * r);
+    int64_t *pcount = a.take<int64_t>((size_t)b.count * nb * k);
+    const int64_t rpb = (n + nb - 1) / nb;
+    const size_t lds = ((size_t)k * r + k) * sizeof(double);
+    const int threads = (int)std::min<int64_t>(256, ((r + 63) / 64) * 64);
+    const dim3 g1((unsigned)nb, (unsigned)b.count);
+    if (lds <= 64 * 1024)
+        update_partial_kernel<<<g1, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
+    else
+        update_partial_global_kernel<<<g1, threads, 0, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
+    const int64_t kr = (int64_t)k * r;
+    const int64_t want = (kr * 64 + 255) / 256;
+    const int64_t cap = b.count <= 1 ? 4096 : std::max<int64_t>(1, 65536 / b.count);
+    const dim3 g2((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
+    update_final_kernel<<<g2, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
+}
+
 }  // namespace asc
 
 using namespace asc;
@@ -224,8 +323,7 @@ extern "C" asc_status asc_normalize_features(float *Y, int64_t n, int64_t r, int
     if (!Y || n < 1 || n >= (int64_t(1) << 31) || r < 1 || r > 65536 || ldy < r || !aligned(Y, 4) ||
         (norms && !aligned(norms, 4)))
         return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
-    const int grid = (int)std::min<int64_t>((n * 64 + NT - 1) / NT, 16384);
-    normalize_kernel<<<grid, NT, 0, as_stream(stream)>>>(Y, n, r, ldy, norms);
+    km_normalize(Y, n, r, ldy, norms, as_stream(stream));
     ASC_LAUNCHED();
     return ASC_OK;
 }
@@ -236,9 +334,7 @@ extern "C" asc_status asc_kmeans_init_rows(const float *F, int64_t n, int64_t r,
     ASC_TRY(check_feat(F, n, r, ldf, who));
     if (!rows || !C || k < 1 || k > 1024 || !aligned(rows, 4) || !aligned(C, 4))
         return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
-    const int64_t total = (int64_t)k * r;
-    init_rows_kernel<<<(int)std::min<int64_t>((total + 255) / 256, 1024), 256, 0, as_stream(stream)>>>(F, n, r, ldf,
-                                                                                                        rows, k, C);
+    km_init_rows(F, n, r, ldf, rows, k, C, KmBatch{}, as_stream(stream));
     ASC_LAUNCHED();
     return ASC_OK;
 }
@@ -249,21 +345,12 @@ extern "C" asc_status asc_kmeans_assign(const float *F, int64_t n, int64_t r, in
     ASC_TRY(check_feat(F, n, r, ldf, who));
     if (!C || !labels || k < 1 || k > 1024 || !aligned(C, 4) || !aligned(labels, 4) || (dist2 && !aligned(dist2, 4)))
         return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
-    const size_t cbytes = (size_t)((k + 63) & ~63) * r * sizeof(float);
-    const int use_lds = cbytes <= 64 * 1024;
-    const int grid = (int)std::min<int64_t>((n * 64 + NT - 1) / NT, 8192);
-    assign_kernel<<<grid, NT, use_lds ? cbytes : 0, as_stream(stream)>>>(F, n, r, ldf, C, k, use_lds, labels, dist2);
+    km_assign(F, n, r, ldf, C, k, labels, dist2, nullptr, KmBatch{}, as_stream(stream));
     ASC_LAUNCHED();
     return ASC_OK;
 }
 
-extern "C" size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k) {
-    Arena a(nullptr);
-    const int nb = update_blocks(n);
-    a.take<double>((size_t)nb * k * r);
-    a.take<int64_t>((size_t)nb * k);
-    return a.size();
-}
+extern "C" size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k) { return km_update_ws(n, r, k, 1); }
 
 extern "C" asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels,
                                         int k, float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream) {
@@ -272,22 +359,7 @@ extern "C" asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, in
     if (!labels || !C || k < 1 || k > 1024 || !aligned(labels, 4) || !aligned(C, 4) || (counts && !aligned(counts, 8)))
         return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
     ASC_TRY(check_ws(ws, ws_bytes, asc_kmeans_update_workspace(n, r, k), who));
-    Arena a(ws);
-    const int nb = update_blocks(n);
-    double *part = a.take<double>((size_t)nb * k * r);
-    int64_t *pcount = a.take<int64_t>((size_t)nb * k);
-    const int64_t rpb = (n + nb - 1) / nb;
-    hipStream_t s = as_stream(stream);
-    const size_t lds = ((size_t)k * r + k) * sizeof(double);
-    const int threads = (int)std::min<int64_t>(256, ((r + 63) / 64) * 64);
-    if (lds <= 64 * 1024)
-        update_partial_kernel<<<nb, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount);
-    else
-        update_partial_global_kernel<<<nb, threads, 0, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount);
-    ASC_LAUNCHED();
-    const int64_t kr = (int64_t)k * r;
-    update_final_kernel<<<(int)std::min<int64_t>((kr * 64 + 255) / 256, 4096), 256, 0, s>>>(nb, r, k, part, pcount, C,
-                                                                                           counts);
+    km_update(F, n, r, ldf, labels, k, C, counts, ws, KmBatch{}, as_stream(stream));
     ASC_LAUNCHED();
     return ASC_OK;
 }

@@ -1,0 +1,34 @@
+// Internal launchers of the normalisation and k-means kernels, for callers
+// inside the library that run many independent problems in one launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace asc {
+
+// count problems, problem b reads feature block b / fdiv (fstride elements
+// apart) and owns centroids b (cstride), labels/distances b (lstride) and
+// initial rows b (rows_stride).  The default is one problem.
+struct KmBatch {
+    int count = 1;
+    int64_t fstride = 0;
+    int fdiv = 1;
+    int64_t cstride = 0;
+    int64_t lstride = 0;
+    int64_t rows_stride = 0;
+};
+
+void km_normalize(float *Y, int64_t n, int64_t r, int64_t ldy, float *norms, hipStream_t s);
+void km_init_rows(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *rows, int k, float *C,
+                  const KmBatch &b, hipStream_t s);
+// dist64 (optional): each row's squared distance to its centroid in float64
+void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
+               float *dist2, double *dist64, const KmBatch &b, hipStream_t s);
+size_t km_update_ws(int64_t n, int64_t r, int k, int count);
+void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k, float *C,
+               int64_t *counts, void *ws, const KmBatch &b, hipStream_t s);
+
+}  // namespace asc

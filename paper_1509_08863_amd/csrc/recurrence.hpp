@@ -30,7 +30,6 @@ constexpr int kMaxGrid = 8192;   // cap of blocks per step launch (grid-stride b
 constexpr unsigned M_FIRST = 1u;  // step 0: T_1 = Lt T_0 (there is no T_{-1})
 constexpr unsigned M_YACC = 2u;   // Y += a_{j+1} T_{j+1}; with M_FIRST: Y = a_0 T_0 + a_1 T_1
 constexpr unsigned M_PART = 4u;   // write float64 partial sums
-constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
 // storage element types: float (4 per 16 B) and bfloat16 bits (8 per 16 B)

@@ -76,3 +76,73 @@ def test_other_entry_points_reject():
     assert L.asc_normalize_features(None, 10, 8, 8, None, None) == _abi.ASC_ERR_INVALID
     g = _abi.asc_graph(0, 0, fake, fake, None, fake)
     assert L.asc_graph_prepare(ctypes.byref(g), fake, 0, None, 0, None) == _abi.ASC_ERR_INVALID
+
+
+@pytest.mark.parametrize("case", ["J=1", "k_max>128", "k_min=0", "eta>eta_max", "eta=0", "p=0", "reps=0",
+                                  "null_gamma", "null_rows", "ws_small", "cols>65536"])
+def test_stability_rejects_before_launch(case):
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x10000)
+    g = _g(n=500)
+    k_min, k_max, J, reps, p, steps, iters, eta_max = 2, 6, 4, 2, 20, 8, 5, 12
+    etas = [2 * k for k in range(k_min, k_max + 1)]
+    gamma, rows, wsb = fake, fake, 1 << 40
+    if case == "J=1":
+        J = 1
+    elif case == "k_max>128":
+        k_max, etas = 129, [4] * 128
+    elif case == "k_min=0":
+        k_min, etas = 0, [4] * 7
+    elif case == "eta>eta_max":
+        etas[-1] = eta_max + 1
+    elif case == "eta=0":
+        etas[0] = 0
+    elif case == "p=0":
+        p = 0
+    elif case == "reps=0":
+        reps = 0
+    elif case == "null_gamma":
+        gamma = None
+    elif case == "null_rows":
+        rows = None
+    elif case == "ws_small":
+        wsb = 1024
+    elif case == "cols>65536":
+        eta_max, J = 40000, 2
+    arr = (ctypes.c_int * len(etas))(*etas)
+    st = L.asc_stability(g, fake, k_min, k_max, arr, J, reps, p, steps, iters, fake, 0, eta_max, J * eta_max, rows,
+                         gamma, None, None, None, None, None, fake, wsb, None)
+    assert st == (_abi.ASC_ERR_WORKSPACE if case == "ws_small" else _abi.ASC_ERR_INVALID), case
+    assert L.asc_last_error()
+
+
+def test_stability_workspace_query():
+    L = _abi.lib()
+    g = _g(n=5000, nnz=50000)
+    etas = [2 * k for k in range(2, 21)]
+    arr = (ctypes.c_int * len(etas))(*etas)
+    need = L.asc_stability_workspace(g, 2, 20, arr, 20, 20, 150, 12, 0, 40)
+    # at least the state store of 151 states x 5000 rows x 800 float32 columns
+    assert need >= 151 * 5000 * 800 * 4
+    assert L.asc_stability_workspace(g, 2, 20, arr, 1, 20, 150, 12, 0, 40) == 0
+
+
+@pytest.mark.parametrize("case", ["J=1", "k=0", "k>128", "ldl<n", "null_ari", "ws_small"])
+def test_ari_rejects_before_launch(case):
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x10000)
+    n, ldl, J, k, ari, wsb = 100, 100, 3, 4, fake, 1 << 20
+    if case == "J=1":
+        J = 1
+    elif case == "k=0":
+        k = 0
+    elif case == "k>128":
+        k = 129
+    elif case == "ldl<n":
+        ldl = 50
+    elif case == "null_ari":
+        ari = None
+    elif case == "ws_small":
+        wsb = 0
+    st = L.asc_ari_pairs(fake, n, ldl, J, k, ari, None, fake, wsb, None)
+    assert st == (_abi.ASC_ERR_WORKSPACE if case == "ws_small" else _abi.ASC_ERR_INVALID), case
