@@ -180,6 +180,37 @@ def copy_bandwidth(dev, nbytes, reps):
     return {"copy_bytes_per_launch": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}
 
 
+def extra_stability(dev, c=6, reps_timed=3):
+    """Stability measure gamma(k) (Eq. stab): planar Gaussian mixture, kNN
+    graph (K = round(ln N)), k over a range, eta_k = 2k, J realisations,
+    k-means replicates; the whole sweep as one call."""
+    import torch
+    import paper_1509_08863_amd as asc
+    cfg = W.CONFIGS[c]
+    t0 = time.time()
+    g, ks, etas, J, (Rs, _), rows = W.stability_config(c)
+    gen_s = time.time() - t0
+    G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev), None)
+    lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, W.config_seeds(c)["lanczos"])).to(dev), 60)
+    ld = (Rs.shape[1] + 3) // 4 * 4
+    R = torch.zeros(g.n, ld, dtype=torch.float32, device=dev)
+    R[:, :Rs.shape[1]] = torch.from_numpy(Rs).to(dev)
+    R = R[:, :Rs.shape[1]]
+    rows_d = torch.from_numpy(rows).to(dev)
+    eta_max = max(etas)
+    args = (G, lmax, ks[0], ks[-1], etas, J, cfg["reps"], cfg["p"], cfg["steps"], cfg["kmeans_iters"], R, eta_max,
+            rows_d)
+    out = asc.stability(*args)
+    ws = asc.stability.last_ws
+    ms = _time(lambda: asc.stability(*args, ws=ws), reps_timed)
+    out = asc.stability(*args, ws=ws)
+    gam = out["gamma"].cpu().numpy()
+    return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ks": [ks[0], ks[-1]], "J": J, "reps": cfg["reps"],
+            "p": cfg["p"], "kmeans_iters": cfg["kmeans_iters"], "ms_per_sweep": round(ms, 3),
+            "gamma": [round(float(x), 4) for x in gam], "k_star": int(ks[int(np.argmax(gam))]),
+            "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +226,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tiling)")
     ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
     ap.add_argument("--copy-probe", action="store_true", help="only time the plain 2 GiB copy kernel and exit")
+    ap.add_argument("--stability-only", type=int, default=0, metavar="C",
+                    help="only time the stability sweep of configuration C (6 or 7) and exit")
     ap.add_argument("--tune", default=None, metavar="RS,VAR",
                     help="fixed float32 launch configuration (slice columns, variant) instead of the autotuner")
     return ap.parse_args()
@@ -211,6 +244,9 @@ def main():
     dev = "cuda:0"
     if args.copy_probe:
         print(json.dumps(copy_bandwidth(dev, 2 << 30, 10)))
+        return
+    if args.stability_only:
+        print(json.dumps(extra_stability(dev, args.stability_only)))
         return
     cfg = W.CONFIGS[args.config]
     seeds = W.config_seeds(args.config)
@@ -393,7 +429,8 @@ def main():
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
-        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev)}
+        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev), "stability": extra_stability(dev, 6),
+                 "stability_large": extra_stability(dev, 7, 1)}
     line = {
         "metric": "Chebyshev-filter SpMM HBM GB/s + ms/filter (fwd, fwd+bwd) at err vs FP64",
         "value": round(gbs32, 2),

@@ -143,6 +143,62 @@ __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F,
     }
 }
 
+// k <= 32: 64/KP rows per wavefront and KP lanes (one per centroid) per row,
+// so small k keeps the lanes busy; the centroids are staged transposed in LDS
+// as float64 (Cd[col][KP]).  The arithmetic per (row, centroid) and the
+// lowest-index argmin are those of assign_kernel (identical labels).
+template <int KP>
+__global__ __launch_bounds__(NT) void assign_grouped_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                            int64_t ldf, const float *__restrict__ Cg, int k,
+                                                            int32_t *__restrict__ labels, float *__restrict__ dist2,
+                                                            double *__restrict__ dist64, Bat bt) {
+#pragma clang fp contract(off)
+    extern __shared__ double Cd[];
+    constexpr int RPW = 64 / KP;
+    F += fblk(bt);
+    Cg += blockIdx.y * bt.c;
+    labels += blockIdx.y * bt.l;
+    if (dist2) dist2 += blockIdx.y * bt.l;
+    if (dist64) dist64 += blockIdx.y * bt.l;
+    for (int64_t q = threadIdx.x; q < (int64_t)KP * r; q += NT) {
+        const int64_t col = q / KP;
+        const int c = (int)(q - col * KP);
+        Cd[q] = c < k ? (double)Cg[(int64_t)c * r + col] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int c = lane % KP;
+    const int sub = lane / KP;
+    const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
+    for (int64_t base = wave0 * RPW; base < n; base += nwaves * RPW) {
+        const int64_t i = base + sub;
+        const bool valid = i < n;
+        const float *f = F + (valid ? i : 0) * ldf;
+        double d = 0.0;
+        for (int64_t col = 0; col < r; ++col) {
+            const double diff = (double)f[col] - Cd[col * KP + c];
+            const double sq = diff * diff;
+            d = d + sq;
+        }
+        int ci = c;
+        if (c >= k) {
+            d = __builtin_huge_val();
+            ci = 0x7fffffff;
+        }
+        for (int off = 1; off < KP; off <<= 1) {
+            const double d2 = __shfl_xor(d, off, 64);
+            const int c2 = __shfl_xor(ci, off, 64);
+            better(d, ci, d2, c2);
+        }
+        if (c == 0 && valid) {
+            labels[i] = ci;
+            if (dist2) dist2[i] = (float)d;
+            if (dist64) dist64[i] = d;
+        }
+    }
+}
+
 // per-block float64 sums of member rows, one thread per column, rows in
 // order (deterministic), partial [block][k][r] and counts [block][k]
 __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
@@ -274,8 +330,30 @@ void km_init_rows(const float *F, int64_t n, int64_t r, int64_t ldf, const int32
     init_rows_kernel<<<grid, 256, 0, s>>>(F, n, r, ldf, rows, k, C, to_bat(b));
 }
 
+template <int KP>
+void assign_grouped(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
+                    float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
+    const int64_t rows_per_block = (NT / 64) * (64 / KP);
+    const int64_t want = (n + rows_per_block - 1) / rows_per_block;
+    const int64_t cap = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
+    assign_grouped_kernel<KP><<<grid, NT, (size_t)KP * r * sizeof(double), s>>>(F, n, r, ldf, C, k, labels, dist2,
+                                                                               dist64, to_bat(b));
+}
+
 void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
+    int kp2 = 2;
+    while (kp2 < k) kp2 *= 2;
+    if (kp2 <= 32 && (size_t)kp2 * r * sizeof(double) <= 64 * 1024) {
+        switch (kp2) {
+            case 2: assign_grouped<2>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            case 4: assign_grouped<4>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            case 8: assign_grouped<8>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            case 16: assign_grouped<16>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            default: assign_grouped<32>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+        }
+    }
     const size_t cbytes = (size_t)((k + 63) & ~63) * r * sizeof(float);
     const int use_lds = cbytes <= 64 * 1024;
     const int64_t want = (n * 64 + NT - 1) / NT;

@@ -97,12 +97,14 @@ def test_normalize_matches_oracle():
     assert np.all(host(Yd)[7] == 0)
 
 
-@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (1000, 96, 50), (333, 7, 3), (64, 130, 200)])
+@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (1000, 96, 50), (333, 7, 3), (64, 130, 200), (1000, 130, 7),
+                                   (777, 5, 2), (2000, 40, 32), (2000, 40, 33), (1500, 256, 32), (301, 3, 1)])
 def test_kmeans_assign_bit_exact(n, r, k):
     rng = np.random.default_rng(n + k)
     F = rng.standard_normal((n, r)).astype(np.float32)
     C = rng.standard_normal((k, r)).astype(np.float32)
-    C[1] = C[0]  # an exact tie: lowest index wins
+    if k > 1:
+        C[1] = C[0]  # an exact tie: lowest index wins
     labels, dist2 = asc.kmeans_assign(block_f32(F), to_dev(C))
     lab_ref, d_ref = oracle.kmeans_assign(F, C)
     np.testing.assert_array_equal(host(labels), lab_ref)

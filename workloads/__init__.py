@@ -198,12 +198,23 @@ def gmm_knn(n: int, d: int, k: int, knn: int, seed: int) -> Graph:
     return Graph(n=n, row_ptr=rp, col_idx=ci, w=None, d2=d2s.astype(np.float32), labels=z, k=k)
 
 
-def gmm2d_points(n: int, k: int, seed: int):
-    """Planar mixture of k Gaussians with different means and spreads:
-    mu_c uniform in [0, 20]^2, sigma_c uniform in [0.3, 1.2], z_i uniform;
-    x_i = mu_{z_i} + sigma_{z_i} N(0, I_2)."""
+def gmm2d_points(n: int, k: int, seed: int, min_sep: float = 5.0):
+    """Planar mixture of k Gaussians with different means and spreads: means
+    uniform in the square [0, 20 sqrt(k/10)]^2, each redrawn until it lies at
+    least min_sep from the previous ones (visible clusters, as in the paper's
+    example; at most 10000 draws per mean), sigma_c uniform in [0.3, 1.2],
+    z_i uniform; x_i = mu_{z_i} + sigma_{z_i} N(0, I_2)."""
     rng = rng_for(seed)
-    mu = rng.uniform(0.0, 20.0, size=(k, 2))
+    box = 20.0 * np.sqrt(k / 10.0)
+    mu = np.zeros((k, 2))
+    for c in range(k):
+        for _ in range(10000):
+            m = rng.uniform(0.0, box, size=2)
+            if c == 0 or np.min(np.linalg.norm(mu[:c] - m, axis=1)) >= min_sep:
+                break
+        else:
+            raise ValueError(f"cannot place {k} means {min_sep} apart in a {box:.1f} square")
+        mu[c] = m
     sd = rng.uniform(0.3, 1.2, size=k)
     z = rng.integers(0, k, size=n)
     x = mu[z] + sd[z, None] * rng.standard_normal((n, 2))
