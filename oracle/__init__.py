@@ -23,7 +23,7 @@ graph filtering of random signals" (ICASSP 2016):
 Parity status of each function is stated in its docstring ("pinned by ..."
 or "parity unpinned").
 """
-from .graph import strength, laplacian_sparse, laplacian_dense, check_graph  # noqa: F401
+from .graph import strength, laplacian_sparse, laplacian_dense, laplacian_normalized, check_graph  # noqa: F401
 from .spectrum import (dense_spectrum, lambda_max_exact, lanczos_tridiag,  # noqa: F401
                        lanczos_lmax, lmax_estimate)
 from .cheb import (jackson, step_coeffs, cheb_coeffs, cheb_eval, cheb_filter,  # noqa: F401

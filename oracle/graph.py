@@ -3,8 +3,14 @@
 W is given as CSR (row_ptr, col_idx, w) with both directions stored; S is
 diagonal with s_i = sum_{j != i} W_ij, the strength of node i.
 
+Also the normalised Laplacian L_n = I - S^{-1/2} W S^{-1/2} of the footnote
+of Sec. 2.1.
+
 Pinned by: L 1 = 0, L symmetric, smallest eigenvalue >= 0 and dim ker L equal to
-the number of connected components (tests/test_oracle_graph.py).
+the number of connected components (tests/test_oracle_graph.py); L_n by the
+closed-form spectra of complete graphs and cycles, the eigenvalue 2 of
+bipartite graphs, spectrum inside [0, 2], and L_n S^{1/2} 1 = 0
+(tests/test_oracle_graph_spectrum.py).
 """
 from __future__ import annotations
 
@@ -32,6 +38,17 @@ def laplacian_sparse(n, row_ptr, col_idx, w=None) -> sp.csr_matrix:
     W = adjacency_sparse(n, row_ptr, col_idx, w)
     s = np.asarray(W.sum(axis=1)).reshape(-1)
     return (sp.diags(s) - W).tocsr()
+
+
+def laplacian_normalized(n, row_ptr, col_idx, w=None) -> sp.csr_matrix:
+    """L_n = I - S^{-1/2} W S^{-1/2} (footnote of Sec. 2.1), float64 sparse;
+    a node of zero strength has S^{-1/2} = 0 there (its row of L_n is e_i)."""
+    W = adjacency_sparse(n, row_ptr, col_idx, w)
+    s = np.asarray(W.sum(axis=1)).reshape(-1)
+    dinv = np.zeros(n)
+    dinv[s > 0] = 1.0 / np.sqrt(s[s > 0])
+    D = sp.diags(dinv)
+    return (sp.identity(n, format="csr") - D @ W @ D).tocsr()
 
 
 def laplacian_dense(n, row_ptr, col_idx, w=None) -> np.ndarray:

@@ -129,3 +129,36 @@ def test_stability_bfloat16_signals_and_single_k():
     assert host(out["gamma"])[0] == 1.0
     for j in range(J):
         assert oracle.ari(host(out["labels"])[0, j], g.labels) == 1.0
+
+
+def test_stability_full_benchmark_size_sampled():
+    # the benchmarked sweep (5000-point planar mixture, k = 2..20, J = 20,
+    # 20 replicates, p = 150) in one call; the oracle recomputes sampled
+    # (k, realisation) cells one by one
+    import workloads as W2
+    c = 6
+    cfg = W2.CONFIGS[c]
+    g, ks, etas, J, (Rs, _), rows = W2.stability_config(c)
+    eta_max = max(etas)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+    s = oracle.strength(g.n, g.row_ptr, g.col_idx, None)
+    lmax = oracle.lmax_estimate(L, s, W2.start_vector(g.n, W2.config_seeds(c)["lanczos"]), 60)
+    G = upload_graph(g)
+    out = asc.stability(G, scalar(lmax), ks[0], ks[-1], etas, J, cfg["reps"], cfg["p"], cfg["steps"],
+                        cfg["kmeans_iters"], block_f32(Rs), eta_max, to_dev(rows))
+    res = {k_: host(v) for k_, v in out.items()}
+    pools = _pools(Rs, J, eta_max)
+    assert np.all(np.abs(res["gamma"]) <= 1.0)
+    for q in range(len(ks)):
+        assert res["gamma"][q] == pytest.approx(np.mean(res["ari"][q]), rel=1e-12)
+    agree = []
+    for q, j in [(0, 3), (8, 0), (9, 11), (18, 19)]:
+        k = ks[q]
+        F, est, traj = oracle.features(L, lmax, k, etas[q], pools[j], cfg["p"], cfg["steps"])
+        if _traj_agree(res["traj"][q, j], traj, k):
+            assert res["lambda_k"][q, j] == est
+        lab, best, ins = oracle.kmeans_replicates(F, k, rows[q, j], cfg["kmeans_iters"])
+        # the chosen replicate's inertia is the oracle's least one
+        assert np.min(res["inertia"][q, j]) == pytest.approx(np.min(ins), rel=1e-4)
+        agree.append(oracle.ari(res["labels"][q, j], lab))
+    assert np.mean(agree) >= 0.97, agree

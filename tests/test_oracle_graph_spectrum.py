@@ -115,3 +115,37 @@ def test_lmax_unweighted_lower_bound():
     s = oracle.strength(g.n, g.row_ptr, g.col_idx, g.w)
     est = oracle.lmax_estimate(L, s, W.start_vector(g.n, 3), 60)
     assert lam[-1] <= est <= 1.02 * lam[-1]
+
+
+@pytest.mark.parametrize("n", [3, 7, 12])
+def test_normalized_laplacian_closed_forms(n):
+    # complete graph K_n: eigenvalues 0 and n/(n-1) (n-1 times)
+    g = W.complete(n)
+    lam = np.linalg.eigvalsh(oracle.laplacian_normalized(g.n, g.row_ptr, g.col_idx).toarray())
+    np.testing.assert_allclose(lam, [0.0] + [n / (n - 1)] * (n - 1), atol=1e-12)
+    # cycle C_n: 1 - cos(2 pi k / n)
+    g = W.cycle(n)
+    lam = np.linalg.eigvalsh(oracle.laplacian_normalized(g.n, g.row_ptr, g.col_idx).toarray())
+    ref = np.sort(1.0 - np.cos(2 * np.pi * np.arange(n) / n))
+    np.testing.assert_allclose(lam, ref, atol=1e-12)
+
+
+def test_normalized_laplacian_invariants():
+    rng = np.random.default_rng(3)
+    g = W.random_weighted(60, 0.1, 4, isolated=3)
+    Ln = oracle.laplacian_normalized(g.n, g.row_ptr, g.col_idx, g.w).toarray()
+    lam = np.linalg.eigvalsh(Ln)
+    assert lam.min() > -1e-12 and lam.max() < 2 + 1e-12
+    np.testing.assert_allclose(Ln, Ln.T, atol=0)
+    s = oracle.strength(g.n, g.row_ptr, g.col_idx, g.w)
+    np.testing.assert_allclose(Ln @ np.sqrt(s), 0.0, atol=1e-12)
+    # isolated nodes: rows of the identity (eigenvalue 1)
+    for i in range(g.n - 3, g.n):
+        e = np.zeros(g.n)
+        e[i] = 1
+        np.testing.assert_array_equal(Ln[i], e)
+    # bipartite (even cycle, path) graphs reach the bound 2
+    for gb in (W.cycle(10), W.path(9)):
+        lb = np.linalg.eigvalsh(oracle.laplacian_normalized(gb.n, gb.row_ptr, gb.col_idx).toarray())
+        assert abs(lb.max() - 2.0) < 1e-12
+    del rng
