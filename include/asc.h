@@ -97,6 +97,16 @@ size_t asc_graph_prepare_workspace(int64_t n, int validate);
 asc_status asc_graph_prepare(const asc_graph *g, double *strength, int validate, void *ws, size_t ws_bytes,
                              void *stream);
 
+/* Normalised Laplacian (footnote of Sec. 2.1): L_n = I - S^{-1/2} W S^{-1/2}.
+ * From a prepared graph g (strengths filled) writes w_out[nnz] = w_e /
+ * sqrt(s_i s_k) (float64 arithmetic, 0 where s_i or s_k is 0; unit weights
+ * when g->w is NULL) and strength_out[n] = 1.  The graph {n, nnz, row_ptr,
+ * col_idx, w_out, strength_out} then makes every entry point apply L_n in
+ * place of L; its largest eigenvalue is at most 2, so lmax = 2 may be passed
+ * without an estimate.  Gradients computed on it are with respect to w_out.
+ * Outputs must not alias g's arrays. */
+asc_status asc_graph_normalize(const asc_graph *g, float *w_out, double *strength_out, void *stream);
+
 /* Step 1 of the algorithm (Sec. 4.1): an upper estimate of lambda_N.
  * Lanczos in float64 from the start vector v0[n] (not normalised; any
  * non-zero vector) for `iters` steps (stops early on breakdown), then

@@ -88,6 +88,15 @@ def graph_prepare(row_ptr: torch.Tensor, col_idx: torch.Tensor, w: torch.Tensor 
     return g
 
 
+def graph_normalized(g: Graph) -> Graph:
+    """The same pattern with w_e / sqrt(s_i s_k) and unit strengths: entry
+    points called on it apply L_n = I - S^-1/2 W S^-1/2 (lmax = 2 is valid)."""
+    wn = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=g.device)[:g.nnz]
+    ones = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    _abi.check(_abi.lib().asc_graph_normalize(g.c(), _ptr(wn) if g.nnz else None, _ptr(ones), _stream()))
+    return Graph(g.row_ptr, g.col_idx, wn, ones)
+
+
 def lmax_estimate(g: Graph, v0: torch.Tensor, iters: int = 60, host: bool = False):
     L = _abi.lib()
     out = torch.empty(1, dtype=torch.float64, device=g.device)

@@ -78,10 +78,41 @@ __global__ void zero_u32(uint32_t *p, int count) {
     if (i < count) p[i] = 0u;
 }
 
+// normalised Laplacian (footnote of Sec. 2.1): w'_e = w_e / sqrt(s_i s_k)
+// in float64 (0 where s_i or s_k is 0) and unit strengths, so that every
+// kernel built on L = S - W applies L_n = I - S^{-1/2} W S^{-1/2}
+__global__ void normalize_weights_kernel(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                         const float *__restrict__ w, const double *__restrict__ s,
+                                         float *__restrict__ wn, double *__restrict__ ones) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double si = s[i];
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const double sk = s[ci[e]];
+        const double we = w ? (double)w[e] : 1.0;
+        wn[e] = (si > 0.0 && sk > 0.0) ? (float)(we / sqrt(si * sk)) : 0.0f;
+    }
+    ones[i] = 1.0;
+}
+
 }  // namespace
 }  // namespace asc
 
 using namespace asc;
+
+extern "C" asc_status asc_graph_normalize(const asc_graph *g, float *w_out, double *strength_out, void *stream) {
+    const char *who = "asc_graph_normalize";
+    ASC_TRY(check_graph_args(g, true, who));
+    if ((g->nnz > 0 && (!w_out || !aligned(w_out, 4))) || !strength_out || !aligned(strength_out, 8))
+        return fail(ASC_ERR_INVALID, "%s: w_out or strength_out NULL or misaligned", who);
+    if (static_cast<const void *>(w_out) == static_cast<const void *>(g->w) || strength_out == g->strength)
+        return fail(ASC_ERR_INVALID, "%s: outputs must not alias the input graph", who);
+    const int64_t n = g->n;
+    normalize_weights_kernel<<<(unsigned)((n + 255) / 256), 256, 0, as_stream(stream)>>>(
+        n, g->row_ptr, g->col_idx, g->w, g->strength, w_out, strength_out);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
 
 extern "C" size_t asc_graph_prepare_workspace(int64_t n, int validate) {
     (void)n;
