@@ -18,6 +18,7 @@ graph filtering of random signals" (ICASSP 2016):
   cluster.py   row normalisation, k-means                         (Sec. 2.2 step 4, Sec. 4.1 step 6, footnote of Sec. 2.1)
   grad.py      Gaussian-kernel weights, loss, adjoint gradients  (extension beyond the paper)
   stability.py adjusted Rand index, stability measure gamma(k)    (Sec. 4.3, Eq. stab)
+  order.py     least polynomial order for a tolerance, m*(rho; delta) (Sec. 2.4, note on m)
   cpu_baseline.c  the same FP64 recurrence over CSR in plain C/OpenMP, for timing
 
 Parity status of each function is stated in its docstring ("pinned by ..."
@@ -35,3 +36,4 @@ from .grad import (gauss_weights, rownorm_loss_grad, cheb_filter_adjoint,  # noq
                    daleckii_krein_M, dW_from_M, dsigma, loss_of_weights, cheb_filter_adjoint_sampled)
 from .stability import (contingency, ari_terms, ari, ari_pairs, gamma, inertia,  # noqa: F401
                         kmeans_replicates, realisation_signals, features, cluster_once, stability)
+from .order import grid_points, band_error, order_errors, m_star  # noqa: F401

@@ -241,6 +241,61 @@ __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, in
     for (int q = threadIdx.x; q < k; q += blockDim.x) pcount[(int64_t)blockIdx.x * k + q] = (int64_t)S[kr + q];
 }
 
+// same with 4 wavefronts per block, each summing its own quarter of the
+// block's rows into its own LDS copy (rows in order, one lane per column);
+// the copies are then added in wavefront order (deterministic)
+__global__ __launch_bounds__(256) void update_partial4_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                              int64_t ldf, const int32_t *__restrict__ labels, int k,
+                                                              int64_t rows_per_block, double *__restrict__ part,
+                                                              int64_t *__restrict__ pcount, Bat bt) {
+    extern __shared__ double S4[];  // 4 x (k*r sums, k counts)
+    const int64_t kr = (int64_t)k * r;
+    const int64_t stride = kr + k;
+    F += fblk(bt);
+    labels += blockIdx.y * bt.l;
+    part += (int64_t)blockIdx.y * gridDim.x * kr;
+    pcount += (int64_t)blockIdx.y * gridDim.x * k;
+    for (int64_t q = threadIdx.x; q < 4 * stride; q += blockDim.x) S4[q] = 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *S = S4 + wave * stride;
+    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t b1 = min(n, b0 + rows_per_block);
+    const int64_t len = b1 > b0 ? b1 - b0 : 0;
+    const int64_t q4 = (len + 3) / 4;
+    const int64_t i0 = min(b1, b0 + wave * q4);
+    const int64_t i1 = min(b1, i0 + q4);
+    constexpr int U = 8;
+    for (int64_t ib = i0; ib < i1; ib += U) {
+        int lab[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
+        for (int64_t col = lane; col < r; col += 64) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (ib + u < i1) ? F[(ib + u) * ldf + col] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lab[u];
+                if (c >= 0 && c < k) S[(int64_t)c * r + col] += (double)v[u];
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (lab[u] >= 0 && lab[u] < k) S[kr + lab[u]] += 1.0;
+        }
+    }
+    __syncthreads();
+    double *out = part + (int64_t)blockIdx.x * kr;
+    for (int64_t q = threadIdx.x; q < kr; q += blockDim.x)
+        out[q] = ((S4[q] + S4[stride + q]) + S4[2 * stride + q]) + S4[3 * stride + q];
+    for (int q = threadIdx.x; q < k; q += blockDim.x)
+        pcount[(int64_t)blockIdx.x * k + q] =
+            (int64_t)S4[kr + q] + (int64_t)S4[stride + kr + q] + (int64_t)S4[2 * stride + kr + q] +
+            (int64_t)S4[3 * stride + kr + q];
+}
+
 // same, for k*r too large for LDS: sums kept in the partial array itself
 __global__ void update_partial_global_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                              const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
@@ -381,7 +436,9 @@ void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t 
     const size_t lds = ((size_t)k * r + k) * sizeof(double);
     const int threads = (int)std::min<int64_t>(256, ((r + 63) / 64) * 64);
     const dim3 g1((unsigned)nb, (unsigned)b.count);
-    if (lds <= 64 * 1024)
+    if (b.count > 1 && 4 * lds <= 64 * 1024)
+        update_partial4_kernel<<<g1, 256, 4 * lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
+    else if (lds <= 64 * 1024)
         update_partial_kernel<<<g1, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
     else
         update_partial_global_kernel<<<g1, threads, 0, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
