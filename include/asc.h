@@ -276,6 +276,22 @@ asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t 
                          double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph, void *stream);
 asc_status asc_batch_destroy(void *plan);
 
+/* Order of the polynomial (note on the choice of m, Sec. 2.4): for every
+ * rho[q] = lambda_c / lambda_N (device, n_rho values in (0, 1)) the errors
+ *   err[q][m-1] = max |h(x_i) - p_m(x_i)| over the grid x_i = cos(pi i/(G-1)),
+ *                 i = 0..G-1 (G = grid), restricted to |x_i - x_c| >= 2 band,
+ * m = 1..m_max, where x_c = 2 rho - 1, h = 1[x <= x_c] and p_m the order-m
+ * approximation of asc_cheb_coeffs (Jackson-damped when jackson != 0), and
+ *   m_star[q][d] = the least m with err[q][m-1] <= delta[d], m_max + 1 if none.
+ * The printed criterion takes the sup over the whole spectrum, which the jump
+ * of h makes unreachable below 1/2; band (a fraction of lambda_N, >= 0) is the
+ * transition width left out.  err may be NULL (then ws holds it, sized by
+ * asc_order_table_workspace).  1 <= m_max <= 8000, 2 <= grid <= 2^22. */
+size_t asc_order_table_workspace(int n_rho, int m_max);
+asc_status asc_order_table(const double *rho, int n_rho, const double *delta, int n_delta, double band, int m_max,
+                           int grid, int jackson, double *err, int32_t *m_star, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* Stability measure for the number of clusters (Sec. 4.3, Eq. stab): for every
  * k = k_min..k_max the algorithm of Sec. 4.1 (steps 2-6) runs on J independent
  * realisations of its random signals, and

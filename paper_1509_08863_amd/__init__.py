@@ -398,6 +398,29 @@ def stability(g: Graph, lmax: torch.Tensor, k_min: int, k_max: int, etas, J: int
     return out
 
 
+def order_table(rho: torch.Tensor, delta: torch.Tensor, band: float, m_max: int, grid: int = 2049,
+                jackson: bool = True):
+    """Least orders m*[q][d] meeting delta[d] outside the band for each
+    rho[q] = lambda_c / lambda_N, and the errors err[q][m-1] (device tensors)."""
+    rho = rho.to(torch.float64).contiguous()
+    delta = delta.to(torch.float64).contiguous()
+    err = torch.empty(rho.numel(), m_max, dtype=torch.float64, device=rho.device)
+    ms = torch.empty(rho.numel(), delta.numel(), dtype=torch.int32, device=rho.device)
+    _abi.check(_abi.lib().asc_order_table(_ptr(rho), rho.numel(), _ptr(delta), delta.numel(), float(band), m_max, grid,
+                                          int(jackson), _ptr(err), _ptr(ms), None, 0, _stream()))
+    return ms, err
+
+
+def order_for(lambda_c: float, lmax: float, delta: float = 0.1, band_rel: float = 0.5, m_max: int = 4000,
+              grid: int = 2049, device="cuda:0") -> int:
+    """Order for one filter: m*(lambda_c / lmax; delta) with the transition
+    band set to band_rel * lambda_c (host int)."""
+    rho = lambda_c / lmax
+    ms, _ = order_table(torch.tensor([rho], dtype=torch.float64, device=device),
+                        torch.tensor([delta], dtype=torch.float64, device=device), band_rel * rho, m_max, grid)
+    return int(ms.cpu()[0, 0])
+
+
 def ari_pairs(labels: torch.Tensor, k: int):
     """Adjusted Rand index of every pair (a, b), a < b, of the J labellings in
     the rows of labels (int32 J x n, values in [0, k)); returns (ari, mean)."""

@@ -24,8 +24,9 @@ def test_delta_one_needs_order_one():
 
 
 def test_undamped_series_overshoots():
-    # without damping the truncated series overshoots near the jump (Gibbs):
-    # the error just outside a thin band stays near 0.09 however large m is
+    # without damping the truncated series does not converge uniformly near
+    # the jump (Gibbs): just outside a thin band the error stays large however
+    # large m is
     e = order.order_errors(0.3, 200, 0.002, G, jackson=False)
     assert e[-1] > 0.05
     assert order.m_star(0.3, 0.05, 200, 0.002, G, jackson=False) == 201
