@@ -19,6 +19,7 @@ graph filtering of random signals" (ICASSP 2016):
   grad.py      Gaussian-kernel weights, loss, adjoint gradients  (extension beyond the paper)
   stability.py adjusted Rand index, stability measure gamma(k)    (Sec. 4.3, Eq. stab)
   order.py     least polynomial order for a tolerance, m*(rho; delta) (Sec. 2.4, note on m)
+  knn.py       K-nearest-neighbour graph, union-symmetrised             (Sec. 5)
   cpu_baseline.c  the same FP64 recurrence over CSR in plain C/OpenMP, for timing
 
 Parity status of each function is stated in its docstring ("pinned by ..."
@@ -37,3 +38,5 @@ from .grad import (gauss_weights, rownorm_loss_grad, cheb_filter_adjoint,  # noq
 from .stability import (contingency, ari_terms, ari, ari_pairs, gamma, inertia,  # noqa: F401
                         kmeans_replicates, realisation_signals, features, cluster_once, stability)
 from .order import grid_points, band_error, order_errors, m_star  # noqa: F401
+from .knn import sqdist_to, knn_bruteforce, union_graph  # noqa: F401
+from .knn import knn as knn_exact  # noqa: F401
