@@ -276,6 +276,29 @@ asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t 
                          double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph, void *stream);
 asc_status asc_batch_destroy(void *plan);
 
+/* K-nearest-neighbour similarity graph (Sec. 5: a K-nearest-neighbours graph
+ * with K ~ log N) from n points X (float32, row i at X[i*ldx], d coordinates,
+ * 1 <= d <= 64), built in two calls that share ws (asc_knn_workspace bytes,
+ * unchanged between them):
+ *  asc_knn: nbr[n][k] (int32) and d2[n][k] (float64) = the k points j != i of
+ *    least |x_i - x_j|^2, computed in float64 from the float32 coordinates
+ *    (added in order), ascending, ties to the lower index; and row_ptr[n+1] of
+ *    the union-symmetrised graph ({i, j} kept when either is a neighbour of the
+ *    other).  fallback_rows (optional, device uint32): how many rows the
+ *    float32 matrix-core proposals could not certify and a float64 scan over all
+ *    points redid.  A point with non-finite coordinates gets nbr = -1 entries.
+ *  asc_knn_graph_fill: after the caller reads nnz = row_ptr[n] and allocates,
+ *    col_idx[nnz] (increasing in each row) and d2[nnz] (float32 of the float64
+ *    distance) of that graph; with asc_gauss_weights it gives the similarity
+ *    weights w = exp(-d2 / sigma^2) of Sec. 2.2.
+ * 1 <= k <= min(32, n - 1), 2 n k < 2^31. */
+size_t asc_knn_workspace(int64_t n, int d, int k);
+asc_status asc_knn(const float *X, int64_t n, int d, int64_t ldx, int k, int32_t *nbr, double *d2, int32_t *row_ptr,
+                   uint32_t *fallback_rows, void *ws, size_t ws_bytes, void *stream);
+asc_status asc_knn_graph_fill(const float *X, int64_t n, int d, int64_t ldx, int k, const int32_t *nbr,
+                              const int32_t *row_ptr, int32_t *col_idx, float *d2, void *ws, size_t ws_bytes,
+                              void *stream);
+
 /* Order of the polynomial (note on the choice of m, Sec. 2.4): for every
  * rho[q] = lambda_c / lambda_N (device, n_rho values in (0, 1)) the errors
  *   err[q][m-1] = max |h(x_i) - p_m(x_i)| over the grid x_i = cos(pi i/(G-1)),

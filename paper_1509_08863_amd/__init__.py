@@ -398,6 +398,31 @@ def stability(g: Graph, lmax: torch.Tensor, k_min: int, k_max: int, etas, J: int
     return out
 
 
+def knn_graph(X: torch.Tensor, k: int):
+    """K-nearest-neighbour graph of the rows of X (float32 n x d, d <= 64):
+    returns dict with nbr [n][k] int32, nbr_d2 [n][k] float64 (exact, ties to
+    the lower index), row_ptr / col_idx (int32) and d2 (float32) of the
+    union-symmetrised graph, and fallback_rows (device uint32)."""
+    L = _abi.lib()
+    n, d = X.shape
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit column stride")
+    dev = X.device
+    ws = workspace(L.asc_knn_workspace(n, d, k), dev)
+    nbr = torch.empty(n, k, dtype=torch.int32, device=dev)
+    nd2 = torch.empty(n, k, dtype=torch.float64, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    fb = torch.zeros(1, dtype=torch.int32, device=dev)
+    _abi.check(L.asc_knn(_ptr(X), n, d, X.stride(0), k, _ptr(nbr), _ptr(nd2), _ptr(row_ptr), _ptr(fb), _ptr(ws),
+                         ws.numel(), _stream()))
+    nnz = int(row_ptr[n].item())
+    col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+    d2 = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)[:nnz]
+    _abi.check(L.asc_knn_graph_fill(_ptr(X), n, d, X.stride(0), k, _ptr(nbr), _ptr(row_ptr), _ptr(col_idx), _ptr(d2),
+                                    _ptr(ws), ws.numel(), _stream()))
+    return {"nbr": nbr, "nbr_d2": nd2, "row_ptr": row_ptr, "col_idx": col_idx, "d2": d2, "fallback_rows": fb}
+
+
 def order_table(rho: torch.Tensor, delta: torch.Tensor, band: float, m_max: int, grid: int = 2049,
                 jackson: bool = True):
     """Least orders m*[q][d] meeting delta[d] outside the band for each

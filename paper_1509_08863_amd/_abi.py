@@ -83,6 +83,9 @@ SIGNATURES = {
     "asc_batch_run": (I32, [P, P, P, I64, P, I64, P, P, P, SZ, I32, P]),
     "asc_batch_destroy": (I32, [P]),
     "asc_graph_normalize": (I32, [GP, P, P, P]),
+    "asc_knn_workspace": (SZ, [I64, I32, I32]),
+    "asc_knn": (I32, [P, I64, I32, I64, I32, P, P, P, P, P, SZ, P]),
+    "asc_knn_graph_fill": (I32, [P, I64, I32, I64, I32, P, P, P, P, P, SZ, P]),
     "asc_order_table_workspace": (SZ, [I32, I32]),
     "asc_order_table": (I32, [P, I32, P, I32, D, I32, I32, I32, P, P, P, SZ, P]),
     "asc_stability_workspace": (SZ, [GP, I32, I32, P, I32, I32, I32, I32, I32, I64]),
