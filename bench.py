@@ -211,6 +211,26 @@ def extra_stability(dev, c=6, reps_timed=3):
             "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1)}
 
 
+def extra_knn_build(dev, n=200_000, d=16, k=10):
+    """K-nearest-neighbour graph of the gradient workload's points (16-D,
+    20-component mixture), built on the device: float32 MFMA proposals over
+    all pairs, float64 selection, union graph; then Gaussian weights."""
+    import torch
+    import paper_1509_08863_amd as asc
+    x, _ = W.gmm_points(n, d, 20, W.config_seeds(5)["graph"])
+    X = torch.from_numpy(x.astype(np.float32)).to(dev)
+    out = asc.knn_graph(X, k)
+    ms = _time(lambda: asc.knn_graph(X, k), 3)
+    t0 = time.time()
+    W.gmm_knn(n, d, 20, k, W.config_seeds(5)["graph"])
+    host_s = time.time() - t0
+    flops = 2.0 * n * n * ((d + 3) // 4 * 4)
+    return {"n": n, "d": d, "k": k, "nnz": int(out["col_idx"].numel()), "ms_graph": round(ms, 3),
+            "fallback_rows": int(out["fallback_rows"].cpu()[0]),
+            "mfma_tflops_whole_build": round(flops / (ms * 1e-3) / 1e12, 2), "mfma_fp32_peak_tflops": 157.3,
+            "host_kdtree_s": round(host_s, 2)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +246,7 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tiling)")
     ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
     ap.add_argument("--copy-probe", action="store_true", help="only time the plain 2 GiB copy kernel and exit")
+    ap.add_argument("--knn-only", action="store_true", help="only time the kNN graph construction and exit")
     ap.add_argument("--stability-only", type=int, default=0, metavar="C",
                     help="only time the stability sweep of configuration C (6 or 7) and exit")
     ap.add_argument("--tune", default=None, metavar="RS,VAR",
@@ -244,6 +265,9 @@ def main():
     dev = "cuda:0"
     if args.copy_probe:
         print(json.dumps(copy_bandwidth(dev, 2 << 30, 10)))
+        return
+    if args.knn_only:
+        print(json.dumps(extra_knn_build(dev)))
         return
     if args.stability_only:
         print(json.dumps(extra_stability(dev, args.stability_only)))
@@ -429,7 +453,8 @@ def main():
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
-        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev), "stability": extra_stability(dev, 6),
+        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev), "knn_build": extra_knn_build(dev),
+                 "stability": extra_stability(dev, 6),
                  "stability_large": extra_stability(dev, 7, 1)}
     line = {
         "metric": "Chebyshev-filter SpMM HBM GB/s + ms/filter (fwd, fwd+bwd) at err vs FP64",

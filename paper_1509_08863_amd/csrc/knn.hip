@@ -7,9 +7,9 @@
 // in d/4 instructions).  That float32 form only proposes candidates; the
 // neighbours themselves are decided on exact float64 distances, so the result
 // is the exact K-nearest set with ties to the lower index:
-//   A. per (query row, lane class j mod 16) the H nearest by the float32 form
-//      (64 candidates per row);
-//   B. one wavefront per row recomputes the 64 candidates in float64 and keeps
+//   A. per (query row, lane class j mod 16) the H = 8 nearest by the float32
+//      form (128 candidates per row);
+//   B. one wavefront per row recomputes the 128 candidates in float64 and keeps
 //      the K least (distance, index).  The row is certified when its K-th
 //      exact distance is below cut - e, where cut is the least of the 16
 //      classes' H-th proposals (no point left out can be nearer than cut - e)
@@ -26,13 +26,14 @@ namespace asc {
 namespace {
 
 constexpr int NT = 256;
-constexpr int H = 4;            // proposals kept per (row, lane class)
+constexpr int H = 8;            // proposals kept per (row, lane class)
 constexpr int NCAND = 16 * H;   // proposals per row
+static_assert(NCAND % 64 == 0, "proposals are split evenly over a wavefront");
 constexpr int QW = 32;          // query rows per wavefront (two 16-row tiles)
 constexpr int QB = 4 * QW;      // query rows per block
 constexpr int kMaxK = 32;
 constexpr int kMaxD = 64;
-constexpr int kFallbackBlocks = 16;
+constexpr int kFallbackBlocks = 64;
 constexpr int kScanTile = 2048;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -43,8 +44,8 @@ struct KnnWs {
     uint32_t *nmax;      // max |x|^2 as float bits
     uint32_t *nflag;     // rows that needed the float64 scan
     int32_t *flag_list;  // [n]
-    float *cand_d;       // [n][64]
-    int32_t *cand_j;     // [n][64]
+    float *cand_d;       // [n][NCAND]
+    int32_t *cand_j;     // [n][NCAND]
     double *scratch;     // [kFallbackBlocks][n]
     int32_t *cnt;        // [n] reverse-list lengths, then cursors
     int64_t *rev_off;    // [n + 1]
@@ -162,6 +163,11 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
                 hj[g][v][h] = -1;
             }
         }
+    // the MFMA accumulates d2 directly: C starts at |x_q|^2 + |x_j|^2 and A holds -2 x_q
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int s = 0; s < DS; ++s) a[g][s] *= -2.0f;
     for (int64_t c0 = 0; c0 < n; c0 += CB) {
         __syncthreads();
         for (int q = threadIdx.x; q < CB * 4 * DS; q += NT) {
@@ -172,23 +178,35 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
         for (int p = threadIdx.x; p < CB; p += NT) ns[p] = (c0 + p < n) ? nrm[c0 + p] : 0.0f;
         __syncthreads();
         const int pend = (int)min<int64_t>(CB, n - c0);
-        for (int t = 0; t < pend; t += 16) {
+        // software pipeline: the MFMAs of tile t + 16 are issued before the
+        // proposals of tile t are processed
+        v4f cur[2], nxt[2];
+        auto tile_mfma = [&](int t, v4f (&acc)[2]) {
             float b[DS];
 #pragma unroll
             for (int s = 0; s < DS; ++s) b[s] = xs[(t + li) * DP + 4 * s + lk];
-            const int64_t j = c0 + t + li;
             const float nc = ns[t + li];
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
-                v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc[g] = v4f{nq[g][0] + nc, nq[g][1] + nc, nq[g][2] + nc, nq[g][3] + nc};
 #pragma unroll
-                for (int s = 0; s < DS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][s], b[s], acc, 0, 0, 0);
-                if (j < n) {
+                for (int s = 0; s < DS; ++s)
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][s], b[s], acc[g], 0, 0, 0);
+            }
+        };
+        tile_mfma(0, cur);
+        for (int t = 0; t < pend; t += 16) {
+            if (t + 16 < pend) tile_mfma(t + 16, nxt);
+            const int64_t j = c0 + t + li;
+            if (j < n) {
+#pragma unroll
+                for (int g = 0; g < 2; ++g)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if ((int)j != qi[g][v]) propose(hd[g][v], hj[g][v], nq[g][v] + nc - 2.0f * acc[v], (int)j);
-                }
+                        if ((int)j != qi[g][v]) propose(hd[g][v], hj[g][v], cur[g][v], (int)j);
             }
+            cur[0] = nxt[0];
+            cur[1] = nxt[1];
         }
     }
 #pragma unroll
@@ -225,29 +243,40 @@ __device__ __forceinline__ void lexmin(double &d, int &j, double d2, int j2) {
     }
 }
 
-// B: one wavefront per row, lane = proposal
+// B: one wavefront per row, NCAND / 64 proposals per lane
 __global__ __launch_bounds__(NT) void knn_exact_kernel(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
                                                        const float *__restrict__ nrm, const uint32_t *__restrict__ nmax,
                                                        int K, const float *__restrict__ cand_d,
                                                        const int32_t *__restrict__ cand_j, int32_t *__restrict__ nbr,
                                                        double *__restrict__ nd2, int32_t *__restrict__ flag_list,
                                                        uint32_t *__restrict__ nflag) {
+    constexpr int PL = NCAND / 64;
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
     if (i >= n) return;  // uniform per wavefront
-    const int j = cand_j[i * NCAND + lane];
-    const float gd = cand_d[i * NCAND + lane];
-    double de = __builtin_huge_val();
-    if (j >= 0) de = exact_d2(X, ldx, d, i, j);
-    const bool valid = j >= 0 && de < __builtin_huge_val();  // NaN (non-finite coordinates) is no candidate
-    // least H-th proposal over the 16 lane classes (+inf: that class is complete)
-    float cut = (lane % H == H - 1) ? (j >= 0 ? gd : __builtin_inff()) : __builtin_inff();
+    int jj[PL];
+    double de[PL];
+    bool valid[PL], taken[PL];
+    // the least H-th proposal over the 16 lane classes (+inf: that class is complete)
+    float cut = __builtin_inff();
+#pragma unroll
+    for (int p = 0; p < PL; ++p) {
+        const int slot = lane + 64 * p;
+        jj[p] = cand_j[i * NCAND + slot];
+        const float gd = cand_d[i * NCAND + slot];
+        de[p] = jj[p] >= 0 ? exact_d2(X, ldx, d, i, jj[p]) : __builtin_huge_val();
+        valid[p] = jj[p] >= 0 && de[p] < __builtin_huge_val();  // NaN (non-finite coordinates) is no candidate
+        taken[p] = false;
+        if (slot % H == H - 1) cut = fminf(cut, jj[p] >= 0 ? gd : __builtin_inff());
+    }
     for (int off = 32; off > 0; off >>= 1) cut = fminf(cut, __shfl_xor(cut, off, 64));
-    bool taken = false;
     double kth = 0.0;
     for (int t = 0; t < K; ++t) {
-        double bd = (valid && !taken) ? de : __builtin_huge_val();
-        int bj = (valid && !taken) ? j : INT_MAX;
+        double bd = __builtin_huge_val();
+        int bj = INT_MAX;
+#pragma unroll
+        for (int p = 0; p < PL; ++p)
+            if (valid[p] && !taken[p]) lexmin(bd, bj, de[p], jj[p]);
         for (int off = 1; off < 64; off <<= 1) {
             const double d2 = __shfl_xor(bd, off, 64);
             const int j2 = __shfl_xor(bj, off, 64);
@@ -257,7 +286,9 @@ __global__ __launch_bounds__(NT) void knn_exact_kernel(const float *__restrict__
             nbr[i * K + t] = bj == INT_MAX ? -1 : bj;
             nd2[i * K + t] = bd;
         }
-        if (valid && j == bj) taken = true;
+#pragma unroll
+        for (int p = 0; p < PL; ++p)
+            if (valid[p] && jj[p] == bj) taken[p] = true;
         kth = bd;
     }
     // float32 error bound of the proposals: (2d + 8) u (|x_i|^2 + max |x|^2), u = 2^-24, with margin
@@ -302,7 +333,7 @@ __global__ __launch_bounds__(NT) void knn_fallback_kernel(const float *__restric
             if (threadIdx.x == 0) {
                 for (int w = 1; w < NT / 64; ++w) lexmin(bd, bj, rd[w], rj[w]);
                 // no finite distance left (non-finite coordinates): no neighbour
-                const bool found = bj != INT_MAX;
+                const bool found = bd < __builtin_huge_val();
                 nbr[i * K + t] = found ? bj : -1;
                 nd2[i * K + t] = bd;
                 if (found) dd[bj] = __builtin_huge_val();
