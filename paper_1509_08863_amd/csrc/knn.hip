@@ -7,11 +7,11 @@
 // in d/4 instructions).  That float32 form only proposes candidates; the
 // neighbours themselves are decided on exact float64 distances, so the result
 // is the exact K-nearest set with ties to the lower index:
-//   A. per (query row, lane class j mod 16) the H = 8 nearest by the float32
-//      form (128 candidates per row);
-//   B. one wavefront per row recomputes the 128 candidates in float64 and keeps
+//   A. per (query, lane class) the H = 10 nearest by the float32 form (4
+//      classes: 40 candidates per query);
+//   B. one wavefront per row recomputes the 40 candidates in float64 and keeps
 //      the K least (distance, index).  The row is certified when its K-th
-//      exact distance is below cut - e, where cut is the least of the 16
+//      exact distance is below cut - e, where cut is the least of the 4
 //      classes' H-th proposals (no point left out can be nearer than cut - e)
 //      and e bounds the float32 error of the proposals;
 //   C. rows that fail (rare) are redone by a float64 scan over all points;
@@ -26,9 +26,10 @@ namespace asc {
 namespace {
 
 constexpr int NT = 256;
-constexpr int H = 8;            // proposals kept per (row, lane class)
-constexpr int NCAND = 16 * H;   // proposals per row
-static_assert(NCAND % 64 == 0, "proposals are split evenly over a wavefront");
+constexpr int H = 10;           // proposals kept per (query, lane class)
+constexpr int NCLASS = 4;       // lane classes per query (candidate rows 4c..4c+3 of every tile)
+constexpr int NCAND = NCLASS * H;  // proposals per query
+static_assert(NCAND <= 64, "one proposal per lane in the exact selection");
 constexpr int QW = 32;          // query rows per wavefront (two 16-row tiles)
 constexpr int QB = 4 * QW;      // query rows per block
 constexpr int kMaxK = 32;
@@ -121,10 +122,11 @@ __device__ __forceinline__ void propose(float (&hd)[H], int (&hj)[H], float dv, 
     }
 }
 
-// A: a wavefront owns 32 query rows (two 16 x 4 A operands per k step); the
-// block stages 256 candidate points in LDS and every wavefront sweeps them in
-// 16-point tiles.  Output layout of the 16 x 16 x 4 MFMA: lane l holds the
-// tile's column l % 16 (candidate) for rows 4 (l / 16) + v, v = 0..3.
+// A: a wavefront owns 32 queries, the B operands (columns) of two 16 x 16
+// tiles; the block stages candidate points in LDS and every wavefront sweeps
+// them 16 at a time as the A operand (rows).  In the 16 x 16 x 4 MFMA output
+// lane l holds column l % 16 (its query) for rows 4 (l / 16) + v, v = 0..3: the
+// lane sees 4 candidates per tile and keeps its class's (l / 16) H nearest.
 template <int DS>
 __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
                                                          const float *__restrict__ nrm, float *__restrict__ cand_d,
@@ -136,38 +138,28 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t qbase = (int64_t)blockIdx.x * QB + wave * QW;
-    float a[2][DS];
+    // B operands: -2 x_q (the MFMA then accumulates |x_q|^2 + |x_j|^2 - 2 x_q.x_j)
+    float bq[2][DS];
+    int qi[2];
+    float nq[2];
+    float hd[2][H];
+    int hj[2][H];
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
         const int64_t q = qbase + 16 * g + li;
 #pragma unroll
         for (int s = 0; s < DS; ++s) {
             const int c = 4 * s + lk;
-            a[g][s] = (q < n && c < d) ? X[q * ldx + c] : 0.0f;
+            bq[g][s] = (q < n && c < d) ? -2.0f * X[q * ldx + c] : 0.0f;
+        }
+        qi[g] = q < n ? (int)q : -1;
+        nq[g] = q < n ? nrm[q] : 0.0f;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            hd[g][h] = __builtin_inff();
+            hj[g][h] = -1;
         }
     }
-    float nq[2][4];
-    int qi[2][4];
-    float hd[2][4][H];
-    int hj[2][4][H];
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t q = qbase + 16 * g + 4 * lk + v;
-            qi[g][v] = q < n ? (int)q : -1;
-            nq[g][v] = q < n ? nrm[q] : 0.0f;
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                hd[g][v][h] = __builtin_inff();
-                hj[g][v][h] = -1;
-            }
-        }
-    // the MFMA accumulates d2 directly: C starts at |x_q|^2 + |x_j|^2 and A holds -2 x_q
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int s = 0; s < DS; ++s) a[g][s] *= -2.0f;
     for (int64_t c0 = 0; c0 < n; c0 += CB) {
         __syncthreads();
         for (int q = threadIdx.x; q < CB * 4 * DS; q += NT) {
@@ -182,45 +174,43 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
         // proposals of tile t are processed
         v4f cur[2], nxt[2];
         auto tile_mfma = [&](int t, v4f (&acc)[2]) {
-            float b[DS];
+            float a[DS];
 #pragma unroll
-            for (int s = 0; s < DS; ++s) b[s] = xs[(t + li) * DP + 4 * s + lk];
-            const float nc = ns[t + li];
+            for (int s = 0; s < DS; ++s) a[s] = xs[(t + li) * DP + 4 * s + lk];
+            const float n0 = ns[t + 4 * lk], n1 = ns[t + 4 * lk + 1], n2 = ns[t + 4 * lk + 2], n3 = ns[t + 4 * lk + 3];
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
-                acc[g] = v4f{nq[g][0] + nc, nq[g][1] + nc, nq[g][2] + nc, nq[g][3] + nc};
+                acc[g] = v4f{nq[g] + n0, nq[g] + n1, nq[g] + n2, nq[g] + n3};
 #pragma unroll
                 for (int s = 0; s < DS; ++s)
-                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g][s], b[s], acc[g], 0, 0, 0);
+                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bq[g][s], acc[g], 0, 0, 0);
             }
         };
         tile_mfma(0, cur);
         for (int t = 0; t < pend; t += 16) {
             if (t + 16 < pend) tile_mfma(t + 16, nxt);
-            const int64_t j = c0 + t + li;
-            if (j < n) {
+            const int64_t j0 = c0 + t + 4 * lk;
 #pragma unroll
-                for (int g = 0; g < 2; ++g)
+            for (int g = 0; g < 2; ++g)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if ((int)j != qi[g][v]) propose(hd[g][v], hj[g][v], cur[g][v], (int)j);
-            }
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t j = j0 + v;
+                    if (j < n && (int)j != qi[g]) propose(hd[g], hj[g], cur[g][v], (int)j);
+                }
             cur[0] = nxt[0];
             cur[1] = nxt[1];
         }
     }
 #pragma unroll
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < 2; ++g) {
+        if (qi[g] < 0) continue;
+        const int64_t base = (int64_t)qi[g] * NCAND + lk * H;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            if (qi[g][v] < 0) continue;
-            const int64_t base = (int64_t)qi[g][v] * NCAND + li * H;
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                cand_d[base + h] = hd[g][v][h];
-                cand_j[base + h] = hj[g][v][h];
-            }
+        for (int h = 0; h < H; ++h) {
+            cand_d[base + h] = hd[g][h];
+            cand_j[base + h] = hj[g][h];
         }
+    }
 }
 
 __device__ __forceinline__ double exact_d2(const float *__restrict__ X, int64_t ldx, int d, int64_t i, int64_t j) {
@@ -243,40 +233,28 @@ __device__ __forceinline__ void lexmin(double &d, int &j, double d2, int j2) {
     }
 }
 
-// B: one wavefront per row, NCAND / 64 proposals per lane
+// B: one wavefront per row, one proposal per lane (lanes >= NCAND hold none)
 __global__ __launch_bounds__(NT) void knn_exact_kernel(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
                                                        const float *__restrict__ nrm, const uint32_t *__restrict__ nmax,
                                                        int K, const float *__restrict__ cand_d,
                                                        const int32_t *__restrict__ cand_j, int32_t *__restrict__ nbr,
                                                        double *__restrict__ nd2, int32_t *__restrict__ flag_list,
                                                        uint32_t *__restrict__ nflag) {
-    constexpr int PL = NCAND / 64;
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
     if (i >= n) return;  // uniform per wavefront
-    int jj[PL];
-    double de[PL];
-    bool valid[PL], taken[PL];
-    // the least H-th proposal over the 16 lane classes (+inf: that class is complete)
-    float cut = __builtin_inff();
-#pragma unroll
-    for (int p = 0; p < PL; ++p) {
-        const int slot = lane + 64 * p;
-        jj[p] = cand_j[i * NCAND + slot];
-        const float gd = cand_d[i * NCAND + slot];
-        de[p] = jj[p] >= 0 ? exact_d2(X, ldx, d, i, jj[p]) : __builtin_huge_val();
-        valid[p] = jj[p] >= 0 && de[p] < __builtin_huge_val();  // NaN (non-finite coordinates) is no candidate
-        taken[p] = false;
-        if (slot % H == H - 1) cut = fminf(cut, jj[p] >= 0 ? gd : __builtin_inff());
-    }
+    const int j = lane < NCAND ? cand_j[i * NCAND + lane] : -1;
+    const float gd = lane < NCAND ? cand_d[i * NCAND + lane] : __builtin_inff();
+    const double de = j >= 0 ? exact_d2(X, ldx, d, i, j) : __builtin_huge_val();
+    const bool valid = j >= 0 && de < __builtin_huge_val();  // NaN (non-finite coordinates) is no candidate
+    // the least H-th proposal over the lane classes (+inf: that class is complete)
+    float cut = (lane < NCAND && lane % H == H - 1) ? (j >= 0 ? gd : __builtin_inff()) : __builtin_inff();
     for (int off = 32; off > 0; off >>= 1) cut = fminf(cut, __shfl_xor(cut, off, 64));
+    bool taken = false;
     double kth = 0.0;
     for (int t = 0; t < K; ++t) {
-        double bd = __builtin_huge_val();
-        int bj = INT_MAX;
-#pragma unroll
-        for (int p = 0; p < PL; ++p)
-            if (valid[p] && !taken[p]) lexmin(bd, bj, de[p], jj[p]);
+        double bd = (valid && !taken) ? de : __builtin_huge_val();
+        int bj = (valid && !taken) ? j : INT_MAX;
         for (int off = 1; off < 64; off <<= 1) {
             const double d2 = __shfl_xor(bd, off, 64);
             const int j2 = __shfl_xor(bj, off, 64);
@@ -286,9 +264,7 @@ __global__ __launch_bounds__(NT) void knn_exact_kernel(const float *__restrict__
             nbr[i * K + t] = bj == INT_MAX ? -1 : bj;
             nd2[i * K + t] = bd;
         }
-#pragma unroll
-        for (int p = 0; p < PL; ++p)
-            if (valid[p] && jj[p] == bj) taken[p] = true;
+        if (valid && j == bj) taken = true;
         kth = bd;
     }
     // float32 error bound of the proposals: (2d + 8) u (|x_i|^2 + max |x|^2), u = 2^-24, with margin
