@@ -1,0 +1,66 @@
+"""Degenerate inputs through the C ABI against the FP64 oracle: a graph with
+no edges, a single node, one signal column, zero-weight edges."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+import paper_1509_08863_amd as asc
+
+from gpu_util import upload_graph, block_f32, scalar, host, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _edgeless(n):
+    return W.from_edges(n, np.zeros((0, 2), dtype=np.int64))
+
+
+@pytest.mark.parametrize("n", [1, 7, 300])
+def test_edgeless_graph_filter_and_moments(n):
+    # L = 0, so L~ = -I for any lmax > 0 and Y = p(-1) R
+    g = _edgeless(n)
+    G = upload_graph(g, unit_as_null=True)
+    assert host(G.strength).tolist() == [0.0] * n
+    r, p, lmax = 5, 20, 1.0
+    Rs, R64 = W.signals(n, r, 3)
+    a = oracle.cheb_coeffs(0.3, lmax, p)
+    Y = host(asc.cheb_filter(G, scalar(lmax), to_dev(a), block_f32(Rs)))
+    L = oracle.laplacian_sparse(n, g.row_ptr, g.col_idx, None)
+    Yref = oracle.cheb_filter(L, lmax, a, R64)
+    np.testing.assert_allclose(Yref, oracle.cheb_eval(a, -1.0) * R64, rtol=1e-12, atol=1e-15)
+    assert rel_fro(Y, Yref) <= 1e-6
+    mu = host(asc.cheb_moments(G, scalar(lmax), p, block_f32(Rs)))
+    np.testing.assert_allclose(mu, oracle.moments(L, lmax, p, R64), rtol=1e-6)
+    # every eigenvalue is 0: the count at any cut-off >= 0 estimates n
+    lam, traj = asc.eigcount_lambda_k(G, scalar(lmax), 1, p, 6, block_f32(Rs))
+    est_ref, traj_ref = oracle.dichotomy_moments(L, lmax, 1, p, 6, R64)
+    assert host(traj)[0, 0] == traj_ref[0, 0]
+
+
+def test_edgeless_lmax_estimate_is_zero():
+    g = _edgeless(50)
+    G = upload_graph(g, unit_as_null=True)
+    v0 = W.start_vector(50, 1)
+    lm = asc.lmax_estimate(G, to_dev(v0), 10, host=True)[1]
+    L = oracle.laplacian_sparse(50, g.row_ptr, g.col_idx, None)
+    s = oracle.strength(50, g.row_ptr, g.col_idx, None)
+    assert lm == oracle.lmax_estimate(L, s, v0, 10) == 0.0
+
+
+def test_single_signal_column_and_zero_weight_edges():
+    g = W.random_weighted(400, 0.03, 5)
+    w = g.w.astype(np.float64).copy()
+    w[::7] = 0.0  # zero-weight entries, kept symmetric below
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    A = {(int(i), int(j)): e for e, (i, j) in enumerate(zip(rows, g.col_idx))}
+    for (i, j), e in A.items():
+        if w[e] == 0.0:
+            w[A[(j, i)]] = 0.0
+    G = upload_graph(g, w=w.astype(np.float32))
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w.astype(np.float32).astype(np.float64))
+    lmax = 1.01 * oracle.lambda_max_exact(L)
+    Rs, R64 = W.signals(g.n, 1, 9)
+    a = oracle.cheb_coeffs(0.2 * lmax, lmax, 40)
+    Y = host(asc.cheb_filter(G, scalar(lmax), to_dev(a), block_f32(Rs)))
+    assert rel_fro(Y, oracle.cheb_filter(L, lmax, a, R64)) <= 1e-5
