@@ -434,10 +434,20 @@ def main():
         err["sample"] = f"columns 0..{cols - 1} of R, lambda_max = oracle Lanczos (40 it), lambda_c = 0.17 lambda_max"
         if not args.no_cpu_baseline:
             ms_cpu_full = cpu_s * 1e3 * (r / cols)  # the recurrence is independent per column
-            cpu = {"value": p * bs32 / (ms_cpu_full * 1e-3) / 1e9, "unit": "GB/s", "cores": cb.num_threads(),
-                   "kind": "oracle", "ms_per_filter_extrapolated": ms_cpu_full,
+            threads = cb.num_threads()
+            cpu = {"value": p * bs32 / (ms_cpu_full * 1e-3) / 1e9, "unit": "GB/s", "cores": threads,
+                   "kind": "oracle", "ms_per_filter_extrapolated": ms_cpu_full, "cpu_model": cb.cpu_model(),
                    "sample": f"FP64 C/OpenMP recurrence on {cols} of {r} columns, full graph, p={p}, "
                              f"{cpu_s:.1f} s; scaled by {r}/{cols} to one filter"}
+            # the same oracle on one thread, one column
+            cb.set_threads(1)
+            t1 = time.perf_counter()
+            cb.cheb_filter(n, g.row_ptr, g.col_idx, None, lmax_o, a_o, R64[:, :1])
+            s1 = time.perf_counter() - t1
+            cb.set_threads(threads)
+            ms1 = s1 * 1e3 * r
+            cpu["single_thread"] = {"value": p * bs32 / (ms1 * 1e-3) / 1e9, "ms_per_filter_extrapolated": ms1,
+                                    "sample": f"1 of {r} columns on 1 thread, {s1:.1f} s; scaled by {r}"}
 
     # per-launch roofline of the step kernel: one launch = one recurrence step
     # over one slice of rs columns; the algorithmic bytes of a step are shared

@@ -81,3 +81,14 @@ int oracle_num_threads(void)
     }
     return t;
 }
+
+/* Sets the number of OpenMP threads used by the next calls (0 or less keeps it). */
+void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
