@@ -27,7 +27,7 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            raise RuntimeError("oracle CPU baseline not built: run __graft_entry__.build()")
+            raise RuntimeError("oracle CPU baseline not built: call oracle.cpu_baseline.build()")
         lib = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
         lib.oracle_cheb_filter.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, P, ctypes.c_int,
