@@ -247,6 +247,8 @@ def parse():
     ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
     ap.add_argument("--copy-probe", action="store_true", help="only time the plain 2 GiB copy kernel and exit")
     ap.add_argument("--knn-only", action="store_true", help="only time the kNN graph construction and exit")
+    ap.add_argument("--batch-only", action="store_true", help="only time the 64-graph batch and exit")
+    ap.add_argument("--knn-grad-only", action="store_true", help="only time the kNN-gradient workload and exit")
     ap.add_argument("--stability-only", type=int, default=0, metavar="C",
                     help="only time the stability sweep of configuration C (6 or 7) and exit")
     ap.add_argument("--tune", default=None, metavar="RS,VAR",
@@ -268,6 +270,12 @@ def main():
         return
     if args.knn_only:
         print(json.dumps(extra_knn_build(dev)))
+        return
+    if args.batch_only:
+        print(json.dumps(extra_batch(dev)))
+        return
+    if args.knn_grad_only:
+        print(json.dumps(extra_knn(dev)))
         return
     if args.stability_only:
         print(json.dumps(extra_stability(dev, args.stability_only)))

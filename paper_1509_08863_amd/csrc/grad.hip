@@ -43,6 +43,8 @@ struct AdjArgs {
     float *mt;          // [nnz] accumulated (A T^T)_{k,i} at entry (i,k)
     float *mdiag;       // [n] accumulated M_ii
     double *partials;   // [gridDim.x] <G, T_j>
+    int xcd_bands;      // tiles of XCD x (workgroups b with b mod 8 = x) form one contiguous band of rows
+    int64_t nnz_hint;   // stored entries (host side: picks the kernel variant)
 };
 
 template <int VN>
@@ -77,7 +79,10 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
-template <typename TS, int LPR, unsigned MODE>
+// PF: the next neighbour group's indices, weights and accumulated entries are
+// loaded while the current group's gathers are in flight (pays off on long
+// rows; on short rows the extra registers cost more than it hides)
+template <typename TS, int LPR, unsigned MODE, bool PF>
 __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
     constexpr int VN = St<TS>::VN;
     constexpr int RS = LPR * VN;
@@ -98,7 +103,17 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
     const bool weighted = A.w != nullptr;
     double p_da = 0.0;
     const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // tile schedule: round robin over the grid, or (for locality-ordered
+    // graphs) one contiguous band of tiles per XCD, as in the forward step
+    int64_t tfirst = blockIdx.x, tend = ntiles, tstep = gridDim.x;
+    if (A.xcd_bands && gridDim.x >= 8) {
+        const int64_t xcd = blockIdx.x % 8;
+        const int64_t chunk = (ntiles + 7) / 8;
+        tfirst = xcd * chunk + blockIdx.x / 8;
+        tend = xcd * chunk + chunk < ntiles ? xcd * chunk + chunk : ntiles;
+        tstep = (gridDim.x - xcd + 7) / 8;
+    }
+    for (int64_t tile = tfirst; tile < tend; tile += tstep) {
         const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
         // rows past n still run the neighbour loop (with no entries) so that
         // every lane takes part in the group reductions
@@ -114,21 +129,31 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
         const TS *base = acur + t * VN;
         // loop trip count must be uniform across the lanes of a row group: it is
         // (e1 - e0) for the group's row, identical for its LPR lanes
-        for (int32_t e = e0; e < e1; e += U) {
-            int32_t kc[U];
-            float wc[U];
+        int32_t kc[U];
+        float wc[U];
+        float mtv[U];  // this lane's accumulated entries, loaded with the indices
+        auto load_group = [&](int32_t eg, int32_t (&k_)[U], float (&w_)[U], float (&m_)[U]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                kc[u] = (int32_t)rrow;
-                wc[u] = 0.0f;
-                if (e + u < e1) {
-                    kc[u] = A.ci[e + u];
-                    wc[u] = weighted ? A.w[e + u] : 1.0f;
+                k_[u] = (int32_t)rrow;
+                w_[u] = 0.0f;
+                m_[u] = 0.0f;
+                if (eg + u < e1) {
+                    k_[u] = A.ci[eg + u];
+                    w_[u] = weighted ? A.w[eg + u] : 1.0f;
+                    if ((MODE & B_DW) && (u % LPR) == t) m_[u] = A.mt[eg + u];
                 }
             }
+        };
+        if (PF && e0 < e1) load_group(e0, kc, wc, mtv);
+        for (int32_t e = e0; e < e1; e += U) {
+            if (!PF) load_group(e, kc, wc, mtv);
             raw_t v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+            int32_t kn[U];
+            float wn[U], mn[U];
+            if (PF && e + U < e1) load_group(e + U, kn, wn, mn);
 #pragma unroll
             for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
             if (MODE & B_DW) {
@@ -137,7 +162,15 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
                 for (int u = 0; u < U; ++u) dsum[u] = group_sum<LPR>(dot_raw(v[u], tv));
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if ((u % LPR) == t && e + u < e1) A.mt[e + u] += A.cj * dsum[u];
+                    if ((u % LPR) == t && e + u < e1) A.mt[e + u] = mtv[u] + A.cj * dsum[u];
+            }
+            if (PF && e + U < e1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    kc[u] = kn[u];
+                    wc[u] = wn[u];
+                    mtv[u] = mn[u];
+                }
             }
         }
         float own[VN], g[VN];
@@ -179,11 +212,11 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
     }
 }
 
-template <typename TS, int LPR>
+template <typename TS, int LPR, bool PF>
 hipError_t launch_adj_t(unsigned mode, const AdjArgs &A, int grid, hipStream_t s) {
     switch (mode) {
 #define ASC_ADJ_CASE(m) \
-    case m: adj_step<TS, LPR, m><<<grid, NT, 0, s>>>(A); break;
+    case m: adj_step<TS, LPR, m, PF><<<grid, NT, 0, s>>>(A); break;
         ASC_ADJ_CASE(0) ASC_ADJ_CASE(1) ASC_ADJ_CASE(2) ASC_ADJ_CASE(3) ASC_ADJ_CASE(4) ASC_ADJ_CASE(5)
         ASC_ADJ_CASE(6) ASC_ADJ_CASE(7) ASC_ADJ_CASE(8) ASC_ADJ_CASE(9) ASC_ADJ_CASE(10) ASC_ADJ_CASE(11)
         ASC_ADJ_CASE(12) ASC_ADJ_CASE(13) ASC_ADJ_CASE(14) ASC_ADJ_CASE(15)
@@ -193,23 +226,30 @@ hipError_t launch_adj_t(unsigned mode, const AdjArgs &A, int grid, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_adj(asc_dtype dt, int lpr, unsigned mode, const AdjArgs &A, int grid, hipStream_t s) {
+template <bool PF>
+hipError_t launch_adj_pf(asc_dtype dt, int lpr, unsigned mode, const AdjArgs &A, int grid, hipStream_t s) {
     if (dt == ASC_F32) {
         switch (lpr) {
-            case 2: return launch_adj_t<float, 2>(mode, A, grid, s);
-            case 4: return launch_adj_t<float, 4>(mode, A, grid, s);
-            case 8: return launch_adj_t<float, 8>(mode, A, grid, s);
-            case 16: return launch_adj_t<float, 16>(mode, A, grid, s);
+            case 2: return launch_adj_t<float, 2, PF>(mode, A, grid, s);
+            case 4: return launch_adj_t<float, 4, PF>(mode, A, grid, s);
+            case 8: return launch_adj_t<float, 8, PF>(mode, A, grid, s);
+            case 16: return launch_adj_t<float, 16, PF>(mode, A, grid, s);
         }
     } else {
         switch (lpr) {
-            case 2: return launch_adj_t<uint16_t, 2>(mode, A, grid, s);
-            case 4: return launch_adj_t<uint16_t, 4>(mode, A, grid, s);
-            case 8: return launch_adj_t<uint16_t, 8>(mode, A, grid, s);
-            case 16: return launch_adj_t<uint16_t, 16>(mode, A, grid, s);
+            case 2: return launch_adj_t<uint16_t, 2, PF>(mode, A, grid, s);
+            case 4: return launch_adj_t<uint16_t, 4, PF>(mode, A, grid, s);
+            case 8: return launch_adj_t<uint16_t, 8, PF>(mode, A, grid, s);
+            case 16: return launch_adj_t<uint16_t, 16, PF>(mode, A, grid, s);
         }
     }
     return hipErrorInvalidValue;
+}
+
+// the one-group-ahead index loads are used from 3 groups of 8 entries per row on average
+hipError_t launch_adj(asc_dtype dt, int lpr, unsigned mode, const AdjArgs &A, int grid, hipStream_t s) {
+    const bool long_rows = A.n > 0 && A.rp && A.nnz_hint >= 24 * A.n;
+    return long_rows ? launch_adj_pf<true>(dt, lpr, mode, A, grid, s) : launch_adj_pf<false>(dt, lpr, mode, A, grid, s);
 }
 
 // A_p = a_p G (slice), partial <G, T_p>
@@ -536,6 +576,8 @@ extern "C" asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax
         F.beta = B.beta;
         AdjArgs A{};
         A.n = n;
+        A.xcd_bands = (P.var & 4u) ? 1 : 0;
+        A.nnz_hint = nnz;
         A.rp = g->row_ptr;
         A.ci = g->col_idx;
         A.w = g->w;

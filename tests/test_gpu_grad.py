@@ -187,3 +187,24 @@ def test_state_store_layout_is_independent_of_tuning():
     dw_ref, da_ref = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w32, lmax, a, R64, G64)
     assert rel_fro(d1[0], dw_ref) <= TOL_DW
     assert rel_fro(d1[1], da_ref) <= TOL_DA
+
+
+def test_backward_xcd_band_schedule_gives_the_same_gradients():
+    # variant bit 2 changes only which workgroup takes which rows: dW (summed
+    # per entry by its own row) is bit-identical, dcoeffs (block partials) equal
+    # to rounding
+    r, p = 16, 20
+    g, w64, L, lmax, a, Rs, R64, T = _problem(n=3000, r=r, p=p)
+    Gd = upload_graph(g, w=w64.astype(np.float32))
+    G64 = W.signals_f64(g.n, r, 5).astype(np.float32).astype(np.float64)
+    Rd = block_f32(Rs)
+    _, st0 = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=1)
+    d0 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, st0, 1, block_f32(G64))]
+    try:
+        asc.tune_set(Gd, r, torch.float32, 16, 4)
+        _, st1 = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=1)
+        d1 = [host(t) for t in asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, st1, 1, block_f32(G64))]
+    finally:
+        asc.tune_set(Gd, r, torch.float32, 0, 0)
+    np.testing.assert_array_equal(d1[0], d0[0])
+    np.testing.assert_allclose(d1[1], d0[1], rtol=1e-12, atol=1e-12 * np.max(np.abs(d0[1])))
