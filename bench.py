@@ -205,10 +205,27 @@ def extra_stability(dev, c=6, reps_timed=3):
     ms = _time(lambda: asc.stability(*args, ws=ws), reps_timed)
     out = asc.stability(*args, ws=ws)
     gam = out["gamma"].cpu().numpy()
-    return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ks": [ks[0], ks[-1]], "J": J, "reps": cfg["reps"],
-            "p": cfg["p"], "kmeans_iters": cfg["kmeans_iters"], "ms_per_sweep": round(ms, 3),
-            "gamma": [round(float(x), 4) for x in gam], "k_star": int(ks[int(np.argmax(gam))]),
-            "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1)}
+    res = {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ks": [ks[0], ks[-1]], "J": J, "reps": cfg["reps"],
+           "p": cfg["p"], "kmeans_iters": cfg["kmeans_iters"], "ms_per_sweep": round(ms, 3),
+           "gamma": [round(float(x), 4) for x in gam], "k_star": int(ks[int(np.argmax(gam))]),
+           "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1)}
+    if cfg["n"] <= 10_000:
+        # the oracle on one (k, realisation) cell at the middle k, scaled to the sweep
+        import oracle
+        L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+        s_o = oracle.strength(g.n, g.row_ptr, g.col_idx, None)
+        lmax_o = oracle.lmax_estimate(L, s_o, W.start_vector(g.n, W.config_seeds(c)["lanczos"]), 60)
+        q = len(ks) // 2
+        pool = Rs[:, :eta_max].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.cluster_once(L, lmax_o, ks[q], etas[q], pool, cfg["p"], cfg["steps"], rows[q, 0],
+                            cfg["kmeans_iters"])
+        cell_s = time.perf_counter() - t0
+        res["cpu_oracle"] = {"s_per_cell": round(cell_s, 2), "cells": len(ks) * J,
+                             "s_per_sweep_extrapolated": round(cell_s * len(ks) * J, 1),
+                             "sample": f"one realisation at k = {ks[q]} (FP64 NumPy/SciPy, one thread), "
+                                       f"scaled by the {len(ks) * J} cells"}
+    return res
 
 
 def extra_knn_build(dev, n=200_000, d=16, k=10):
@@ -224,11 +241,15 @@ def extra_knn_build(dev, n=200_000, d=16, k=10):
     t0 = time.time()
     W.gmm_knn(n, d, 20, k, W.config_seeds(5)["graph"])
     host_s = time.time() - t0
+    import oracle
+    t0 = time.time()
+    oracle.knn_exact(x.astype(np.float32), k)
+    oracle_s = time.time() - t0
     flops = 2.0 * n * n * ((d + 3) // 4 * 4)
     return {"n": n, "d": d, "k": k, "nnz": int(out["col_idx"].numel()), "ms_graph": round(ms, 3),
             "fallback_rows": int(out["fallback_rows"].cpu()[0]),
             "mfma_tflops_whole_build": round(flops / (ms * 1e-3) / 1e12, 2), "mfma_fp32_peak_tflops": 157.3,
-            "host_kdtree_s": round(host_s, 2)}
+            "host_kdtree_s": round(host_s, 2), "cpu_oracle_s": round(oracle_s, 2)}
 
 
 def parse():
