@@ -228,6 +228,39 @@ def extra_stability(dev, c=6, reps_timed=3):
     return res
 
 
+def extra_small(dev):
+    """SBM N = 1000, k = 10, mean degree 16, R = 32, p = 50: latency-bound (the
+    working set sits in L2), reported as microseconds per filter."""
+    import torch
+    import paper_1509_08863_amd as asc
+    cfg = W.CONFIGS[1]
+    seeds = W.config_seeds(1)
+    g = W.config_graph(1)
+    G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev),
+                          torch.from_numpy(g.weights_or_ones()).to(dev))
+    R = torch.from_numpy(W.signals(g.n, cfg["r"], seeds["signals"])[0]).to(dev)
+    lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, seeds["lanczos"])).to(dev), 60)
+    p = cfg["p"]
+    a = asc.cheb_coeffs(lmax * 0.05, lmax, p)
+    Y = torch.empty(g.n, cfg["r"], dtype=torch.float32, device=dev)
+    ms = _time(lambda: asc.cheb_filter(G, lmax, a, R, Y), 50)
+    ms_lk = _time(lambda: asc.lambda_k_filter(G, lmax, cfg["k"], p, 12, R, Y), 20)
+    # the same filter captured once in a HIP graph and replayed (no per-launch host overhead)
+    ws = asc.cheb_filter.last_ws
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            asc.cheb_filter(G, lmax, a, R, Y, ws)
+    torch.cuda.current_stream().wait_stream(st)
+    ms_graph = _time(graph.replay, 50)
+    nsl = -(-cfg["r"] // asc.tune_get(G, cfg["r"], torch.float32)[0])
+    return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "us_per_filter": round(ms * 1e3, 1),
+            "step_launches_per_filter": p * nsl, "us_per_step_launch": round(ms * 1e3 / (p * nsl), 2),
+            "us_lambda_k_plus_filter_one_pass": round(ms_lk * 1e3, 1), "us_per_filter_graph_replay": round(ms_graph * 1e3, 1)}
+
+
 def extra_knn_build(dev, n=200_000, d=16, k=10):
     """K-nearest-neighbour graph of the gradient workload's points (16-D,
     20-component mixture), built on the device: float32 MFMA proposals over
@@ -493,7 +526,8 @@ def main():
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
-        extra = {"knn_grad": extra_knn(dev), "batch": extra_batch(dev), "knn_build": extra_knn_build(dev),
+        extra = {"small": extra_small(dev), "knn_grad": extra_knn(dev), "batch": extra_batch(dev),
+                 "knn_build": extra_knn_build(dev),
                  "stability": extra_stability(dev, 6),
                  "stability_large": extra_stability(dev, 7, 1)}
     line = {
