@@ -261,6 +261,32 @@ def extra_small(dev):
             "us_lambda_k_plus_filter_one_pass": round(ms_lk * 1e3, 1), "us_per_filter_graph_replay": round(ms_graph * 1e3, 1)}
 
 
+def extra_mid(dev):
+    """SBM N = 1e5, k = 20, mean degree 20, R = 64, p = 100: the working set
+    (about 120 MB) fits the 256 MB Infinity Cache; compared with the copy of a
+    64 MiB buffer (cache-resident) as well as with the HBM peak."""
+    import torch
+    import paper_1509_08863_amd as asc
+    cfg = W.CONFIGS[2]
+    seeds = W.config_seeds(2)
+    g = W.config_graph(2)
+    G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev),
+                          torch.from_numpy(g.weights_or_ones()).to(dev))
+    r, p = cfg["r"], cfg["p"]
+    R = torch.from_numpy(W.signals(g.n, r, seeds["signals"])[0]).to(dev)
+    lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, seeds["lanczos"])).to(dev), 60)
+    tuned = asc.autotune_filter(G, lmax, R, 3)
+    a = asc.cheb_coeffs(lmax * 0.05, lmax, p)
+    Y = torch.empty(g.n, r, dtype=torch.float32, device=dev)
+    ms = _time(lambda: asc.cheb_filter(G, lmax, a, R, Y), 10)
+    gbs = p * b_step(g.n, g.nnz, r, 4) / (ms * 1e-3) / 1e9
+    llc = copy_bandwidth(dev, 64 << 20, 50)["GBps"]
+    return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ms_per_filter_fwd": round(ms, 3),
+            "gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "copy_gbs_64MiB": round(llc, 1), "frac_of_cache_resident_copy": round(gbs / llc, 4),
+            "tuned": {"slice_cols": tuned[0], "variant": tuned[1]}}
+
+
 def extra_knn_build(dev, n=200_000, d=16, k=10):
     """K-nearest-neighbour graph of the gradient workload's points (16-D,
     20-component mixture), built on the device: float32 MFMA proposals over
@@ -526,7 +552,7 @@ def main():
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
-        extra = {"small": extra_small(dev), "knn_grad": extra_knn(dev), "batch": extra_batch(dev),
+        extra = {"small": extra_small(dev), "mid": extra_mid(dev), "knn_grad": extra_knn(dev), "batch": extra_batch(dev),
                  "knn_build": extra_knn_build(dev),
                  "stability": extra_stability(dev, 6),
                  "stability_large": extra_stability(dev, 7, 1)}
