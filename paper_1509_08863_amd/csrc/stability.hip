@@ -213,8 +213,7 @@ __device__ __forceinline__ double i128_to_f64(__int128 x) {
 // with exact 128-bit integers up to the final division (1 when it is 0/0)
 __global__ __launch_bounds__(NT) void ari_kernel(const int32_t *__restrict__ labels, int64_t n, int64_t ldl, int J,
                                                  int k, double *__restrict__ ari, uint32_t *__restrict__ flags) {
-    extern __shared__ int tab[];  // k * k
-    __shared__ long long red[3][NT / 64];
+    extern __shared__ int tab[];  // k * k (reused for the cross-wavefront sums: 64 KB at k = 128)
     int a = 0;
     int rem = blockIdx.x;
     while (rem >= J - 1 - a) {
@@ -251,23 +250,28 @@ __global__ __launch_bounds__(NT) void ari_kernel(const int32_t *__restrict__ lab
     idx = wave_sum_i64(idx);
     sa = wave_sum_i64(sa);
     sb = wave_sum_i64(sb);
+    // the number of rows that carried valid labels in both
+    long long m = 0;
+    for (int x = threadIdx.x; x < k * k; x += NT) m += tab[x];
+    m = wave_sum_i64(m);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // every read of the table is done: its memory now holds the wavefront sums
+    long long *red = reinterpret_cast<long long *>(tab);  // [4][NT / 64]
     if (lane == 0) {
-        red[0][wave] = idx;
-        red[1][wave] = sa;
-        red[2][wave] = sb;
+        red[0 * (NT / 64) + wave] = idx;
+        red[1 * (NT / 64) + wave] = sa;
+        red[2 * (NT / 64) + wave] = sb;
+        red[3 * (NT / 64) + wave] = m;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        idx = sa = sb = 0;
+        idx = sa = sb = m = 0;
         for (int w = 0; w < NT / 64; ++w) {
-            idx += red[0][w];
-            sa += red[1][w];
-            sb += red[2][w];
+            idx += red[0 * (NT / 64) + w];
+            sa += red[1 * (NT / 64) + w];
+            sb += red[2 * (NT / 64) + w];
+            m += red[3 * (NT / 64) + w];
         }
-        // count the pairs of rows that carried valid labels in both
-        long long m = 0;
-        for (int x = 0; x < k * k; ++x) m += tab[x];
         const __int128 n2 = (__int128)(m * (m - 1) / 2);
         double v = 1.0;
         if (n2 > 0) {
@@ -280,6 +284,11 @@ __global__ __launch_bounds__(NT) void ari_kernel(const int32_t *__restrict__ lab
 }
 
 __global__ void clear_flags_kernel(uint32_t *flags) { flags[0] = 0u; }
+
+// dynamic LDS of ari_kernel: the k x k table, at least the 4 x (NT/64) wavefront sums it later holds
+size_t ari_lds(int k) {
+    return std::max<size_t>((size_t)k * k * sizeof(int), 4 * (NT / 64) * sizeof(long long));
+}
 
 // gamma = mean of the pair ARIs (one wavefront, fixed order)
 __global__ void gamma_kernel(const double *__restrict__ ari, int npairs, double *__restrict__ gamma) {
@@ -487,7 +496,7 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
                                        inertia ? inertia + (int64_t)kk * J * reps : nullptr);
         ASC_LAUNCHED();
         double *ari_k = ari ? ari + (int64_t)kk * npairs : w.ari;
-        ari_kernel<<<npairs, NT, (size_t)k * k * sizeof(int), s>>>(lab_k, n, n, J, k, ari_k, &w.hdr->flags);
+        ari_kernel<<<npairs, NT, ari_lds(k), s>>>(lab_k, n, n, J, k, ari_k, &w.hdr->flags);
         ASC_LAUNCHED();
         gamma_kernel<<<1, 64, 0, s>>>(ari_k, npairs, gamma + kk);
         ASC_LAUNCHED();
@@ -512,7 +521,7 @@ extern "C" asc_status asc_ari_pairs(const int32_t *labels, int64_t n, int64_t ld
     const int npairs = J * (J - 1) / 2;
     clear_flags_kernel<<<1, 1, 0, s>>>(&hdr->flags);
     ASC_LAUNCHED();
-    ari_kernel<<<npairs, NT, (size_t)k * k * sizeof(int), s>>>(labels, n, ldl, J, k, ari, &hdr->flags);
+    ari_kernel<<<npairs, NT, ari_lds(k), s>>>(labels, n, ldl, J, k, ari, &hdr->flags);
     ASC_LAUNCHED();
     if (mean) {
         gamma_kernel<<<1, 64, 0, s>>>(ari, npairs, mean);

@@ -35,6 +35,16 @@ def test_ari_pairs_match_oracle():
     assert host(ari2)[0] == 1.0
 
 
+@pytest.mark.parametrize("k", [1, 2, 5, 127, 128])
+def test_ari_cluster_count_limits(k):
+    rng = np.random.default_rng(k)
+    n = 6000
+    base = rng.integers(0, k, n)
+    labs = [base, np.where(rng.random(n) < 0.6, base, rng.integers(0, k, n)), rng.integers(0, k, n)]
+    ari, _ = asc.ari_pairs(to_dev(np.stack(labs).astype(np.int32)), k)
+    np.testing.assert_allclose(host(ari), oracle.ari_pairs(labs), rtol=1e-13, atol=1e-15)
+
+
 def test_ari_skips_invalid_labels_and_flags_them():
     rng = np.random.default_rng(5)
     n, k = 1000, 4
