@@ -79,6 +79,31 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// Reduce-scatter over the 8 lanes of a row group: lane t holds partial dots
+// p[0..7] of 8 entries and ends with the group's sum for entry t, in 3
+// exchange steps (xor 4, 2, 1), each halving the entries a lane carries:
+// 7 shuffles instead of the 24 of eight separate butterflies.
+__device__ __forceinline__ float group8_reduce_scatter(const float (&p)[8], int t) {
+    const bool b2 = (t & 4) != 0, b1 = (t & 2) != 0, b0 = (t & 1) != 0;
+    float h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float send = b2 ? p[q] : p[q + 4];
+        const float keep = b2 ? p[q + 4] : p[q];
+        h[q] = keep + __shfl_xor(send, 4, 64);  // entry 4 b2 + q
+    }
+    float h2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const float send = b1 ? h[q] : h[q + 2];
+        const float keep = b1 ? h[q + 2] : h[q];
+        h2[q] = keep + __shfl_xor(send, 2, 64);  // entry 4 b2 + 2 b1 + q
+    }
+    const float send = b0 ? h2[0] : h2[1];
+    const float keep = b0 ? h2[1] : h2[0];
+    return keep + __shfl_xor(send, 1, 64);  // entry t
+}
+
 // PF: the next neighbour group's indices, weights and accumulated entries are
 // loaded while the current group's gathers are in flight (pays off on long
 // rows; on short rows the extra registers cost more than it hides)
@@ -157,12 +182,24 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
 #pragma unroll
             for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
             if (MODE & B_DW) {
-                float dsum[U];
+                if constexpr (LPR == 8 && U == 8) {
+                    float pd[8];
 #pragma unroll
-                for (int u = 0; u < U; ++u) dsum[u] = group_sum<LPR>(dot_raw(v[u], tv));
+                    for (int u = 0; u < 8; ++u) pd[u] = dot_raw(v[u], tv);
+                    const float ds = group8_reduce_scatter(pd, t);  // entry e + t, owned by lane t
+                    float own_m = 0.0f;
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if ((u % LPR) == t && e + u < e1) A.mt[e + u] = mtv[u] + A.cj * dsum[u];
+                    for (int u = 0; u < 8; ++u)
+                        if (u == t) own_m = mtv[u];
+                    if (e + t < e1) A.mt[e + t] = own_m + A.cj * ds;
+                } else {
+                    float dsum[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) dsum[u] = group_sum<LPR>(dot_raw(v[u], tv));
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if ((u % LPR) == t && e + u < e1) A.mt[e + u] = mtv[u] + A.cj * dsum[u];
+                }
             }
             if (PF && e + U < e1) {
 #pragma unroll
