@@ -186,19 +186,26 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
                     acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bq[g][s], acc[g], 0, 0, 0);
             }
         };
-        tile_mfma(0, cur);
-        for (int t = 0; t < pend; t += 16) {
-            if (t + 16 < pend) tile_mfma(t + 16, nxt);
-            const int64_t j0 = c0 + t + 4 * lk;
+        // candidate indices in 32 bits (n < 2^31); two tiles per iteration so
+        // the pipelined accumulators alternate instead of being copied
+        const int ni = (int)n;
+        auto consume = [&](int t, const v4f (&acc)[2]) {
+            const int j0 = (int)c0 + t + 4 * lk;
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t j = j0 + v;
-                    if (j < n && (int)j != qi[g]) propose(hd[g], hj[g], cur[g][v], (int)j);
+                    const int j = j0 + v;
+                    if (j < ni && j != qi[g]) propose(hd[g], hj[g], acc[g][v], j);
                 }
-            cur[0] = nxt[0];
-            cur[1] = nxt[1];
+        };
+        tile_mfma(0, cur);
+        for (int t = 0; t < pend; t += 32) {
+            if (t + 16 < pend) tile_mfma(t + 16, nxt);
+            consume(t, cur);
+            if (t + 16 >= pend) break;
+            if (t + 32 < pend) tile_mfma(t + 32, cur);
+            consume(t + 16, nxt);
         }
     }
 #pragma unroll
