@@ -34,7 +34,7 @@ constexpr int QW = 32;          // query rows per wavefront (two 16-row tiles)
 constexpr int QB = 4 * QW;      // query rows per block
 constexpr int kMaxK = 32;
 constexpr int kMaxD = 64;
-constexpr int kFallbackBlocks = 64;
+constexpr int kFallbackBlocks = 64;  // at most; fewer when n is large (scratch <= 1 GiB)
 constexpr int kScanTile = 2048;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -47,7 +47,7 @@ struct KnnWs {
     int32_t *flag_list;  // [n]
     float *cand_d;       // [n][NCAND]
     int32_t *cand_j;     // [n][NCAND]
-    double *scratch;     // [kFallbackBlocks][n]
+    double *scratch;     // [fallback_blocks(n)][n]
     int32_t *cnt;        // [n] reverse-list lengths, then cursors
     int64_t *rev_off;    // [n + 1]
     int32_t *rev;        // [n k]
@@ -56,6 +56,11 @@ struct KnnWs {
 };
 
 int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+// blocks of the float64 fallback scan, each with an n-long scratch row
+int fallback_blocks(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kFallbackBlocks, (int64_t(1) << 30) / (8 * n)));
+}
 
 size_t knn_ws_layout(int64_t n, int k, void *ws, KnnWs *out) {
     Arena a(ws);
@@ -67,7 +72,7 @@ size_t knn_ws_layout(int64_t n, int k, void *ws, KnnWs *out) {
     w.flag_list = a.take<int32_t>(n);
     w.cand_d = a.take<float>((size_t)n * NCAND);
     w.cand_j = a.take<int32_t>((size_t)n * NCAND);
-    w.scratch = a.take<double>((size_t)kFallbackBlocks * n);
+    w.scratch = a.take<double>((size_t)fallback_blocks(n) * n);
     w.cnt = a.take<int32_t>(n);
     w.rev_off = a.take<int64_t>(n + 1);
     w.rev = a.take<int32_t>((size_t)n * k);
@@ -523,7 +528,7 @@ extern "C" asc_status asc_knn(const float *X, int64_t n, int d, int64_t ldx, int
     knn_exact_kernel<<<(unsigned)((n + 3) / 4), NT, 0, s>>>(X, n, d, ldx, w.nrm, w.nmax, k, w.cand_d, w.cand_j, nbr, d2,
                                                            w.flag_list, w.nflag);
     ASC_LAUNCHED();
-    knn_fallback_kernel<<<kFallbackBlocks, NT, 0, s>>>(X, n, d, ldx, k, w.flag_list, w.nflag, w.scratch, nbr, d2);
+    knn_fallback_kernel<<<fallback_blocks(n), NT, 0, s>>>(X, n, d, ldx, k, w.flag_list, w.nflag, w.scratch, nbr, d2);
     ASC_LAUNCHED();
     if (fallback_rows) {
         ASC_HIP(hipMemcpyAsync(fallback_rows, w.nflag, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
