@@ -135,7 +135,8 @@ def extra_knn(dev):
 
 def extra_batch(dev):
     """64 SBMs, N log-uniform in [2e3, 2e5], k in 5..40, mean degree 10-30,
-    R = 48, p = 80, 8 dichotomy steps, one captured launch."""
+    R = 48, p = 80, 8 dichotomy steps, one captured launch of the autotuned
+    plan."""
     import torch
     import paper_1509_08863_amd as asc
     cfg = W.CONFIGS[4]
@@ -157,6 +158,10 @@ def extra_batch(dev):
     lam = torch.empty(len(gs), dtype=torch.float64, device=dev)
     traj = torch.empty(len(gs), steps, 2, dtype=torch.float64, device=dev)
     B = asc.Batch(G, off, ks, r, torch.float32, p, steps)
+    default_plan = B.info()
+    t1 = time.time()
+    tuned = B.autotune(lmax, R, Y, lam, traj, probe_runs=1)
+    tune_s = time.time() - t1
     ms_graph = _time(lambda: B.run(lmax, R, Y, lam, traj, use_graph=True))
     ms_eager = _time(lambda: B.run(lmax, R, Y, lam, traj, use_graph=False))
     ms_steps = max(1, (p + 1) // 2)
@@ -166,7 +171,8 @@ def extra_batch(dev):
     return {"workload": cfg["name"], "graphs": len(gs), "n_total": big.n, "nnz_total": big.nnz,
             "ms_per_batch_graph": round(ms_graph, 3), "ms_per_batch_eager": round(ms_eager, 3),
             "gbs": round(byts / (ms_graph * 1e-3) / 1e9, 1), "algorithmic_bytes": byts, "plan": info,
-            "gen_s": round(gen_s, 1)}
+            "default_plan": default_plan, "tuner_ms_per_batch": round(tuned["ms"], 3),
+            "tune_s": round(tune_s, 1), "gen_s": round(gen_s, 1)}
 
 
 def copy_bandwidth(dev, nbytes, reps):

@@ -266,7 +266,10 @@ asc_status asc_cheb_filter_bwd(const asc_graph *g, const double *lmax, const dou
  * graph on the first call (and again whenever a pointer argument changes) and
  * replayed as one launch.  The plan is host memory owned by the library
  * (free with asc_batch_destroy); the device workspace comes from the caller
- * (asc_batch_workspace bytes) and must not be shared by concurrent runs.
+ * (asc_batch_workspace bytes) and must not be shared by concurrent runs.  The
+ * first run with a given ws pointer uploads the plan's tile list into it and
+ * later runs (and the captured graph) read it from there: keep the contents of
+ * ws between runs, or pass a different pointer.
  * 1 <= p <= 4000. */
 asc_status asc_batch_create(const asc_graph *g, int n_graphs, const int64_t *node_off_host, const int32_t *k_host,
                             int64_t r, asc_dtype sig, int p, int steps, int tile_rows, void **plan);
@@ -275,6 +278,24 @@ asc_status asc_batch_info(const void *plan, int *slice_cols, int *tile_rows, int
 asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
                          double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph, void *stream);
 asc_status asc_batch_destroy(void *plan);
+
+/* Autotuner of a batch plan: times asc_batch_run (eager, probe_runs runs per
+ * candidate after one warm-up run) for every slice width the recurrence
+ * supports up to the one covering r, crossed with tiles of 1, 2, 4, 8, 16 and
+ * 32 passes of the step kernel, on the caller's batch, lmax and R, and
+ * re-plans `plan` with the fastest (ties keep the earlier candidate).
+ * Y, lambda_k and traj are scratch during tuning and hold the result of the
+ * last candidate afterwards; rerun asc_batch_run for the tuned plan's result.
+ * ws needs asc_batch_tune_workspace(plan) bytes (the largest candidate);
+ * asc_batch_workspace(plan) afterwards reports the tuned plan's need, and any
+ * captured graph or uploaded tile list is dropped, also on failure.  The
+ * float64 moment partials are summed per tile, so lambda_k can differ in the
+ * last bits between plans.  Synchronises the stream. 1 <= probe_runs <= 100.
+ * Returns the chosen slice width, tile rows and mean run time in ms. */
+size_t asc_batch_tune_workspace(const void *plan);
+asc_status asc_batch_autotune(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
+                              double *lambda_k, double *traj, int probe_runs, void *ws, size_t ws_bytes,
+                              int *best_slice_cols, int *best_tile_rows, float *best_ms, void *stream);
 
 /* K-nearest-neighbour similarity graph (Sec. 5: a K-nearest-neighbours graph
  * with K ~ log N) from n points X (float32, row i at X[i*ldx], d coordinates,

@@ -350,6 +350,21 @@ class Batch:
         _abi.check(_abi.lib().asc_batch_run(self._h, _ptr(lmax), _ptr(R), _ld(R), _ptr(Y), _ld(Y), _ptr(lambda_k),
                                             _ptr(traj), _ptr(self.ws), self.ws.numel(), int(use_graph), _stream()))
 
+    def autotune(self, lmax: torch.Tensor, R: torch.Tensor, Y: torch.Tensor, lambda_k: torch.Tensor,
+                 traj: torch.Tensor | None = None, probe_runs: int = 1):
+        """Times the candidate slice widths x tile sizes on this batch
+        (asc_batch_autotune), re-plans with the fastest and resizes the
+        workspace; Y, lambda_k and traj are scratch."""
+        L = _abi.lib()
+        ws = workspace(L.asc_batch_tune_workspace(self._h), self.g.device)
+        a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0.0)
+        _abi.check(L.asc_batch_autotune(self._h, _ptr(lmax), _ptr(R), _ld(R), _ptr(Y), _ld(Y), _ptr(lambda_k),
+                                        _ptr(traj), probe_runs, _ptr(ws), ws.numel(), ctypes.byref(a),
+                                        ctypes.byref(b), ctypes.byref(c), _stream()))
+        del ws
+        self.ws = workspace(L.asc_batch_workspace(self._h), self.g.device)
+        return {"slice_cols": a.value, "tile_rows": b.value, "ms": c.value}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _abi.lib().asc_batch_destroy(self._h)

@@ -82,6 +82,9 @@ SIGNATURES = {
                              ctypes.POINTER(ctypes.c_int)]),
     "asc_batch_run": (I32, [P, P, P, I64, P, I64, P, P, P, SZ, I32, P]),
     "asc_batch_destroy": (I32, [P]),
+    "asc_batch_tune_workspace": (SZ, [P]),
+    "asc_batch_autotune": (I32, [P, P, P, I64, P, I64, P, P, I32, P, SZ, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), P]),
     "asc_graph_normalize": (I32, [GP, P, P, P]),
     "asc_knn_workspace": (SZ, [I64, I32, I32]),
     "asc_knn": (I32, [P, I64, I32, I64, I32, P, P, P, P, P, SZ, P]),

@@ -221,6 +221,55 @@ size_t batch_ws_layout(const BatchPlan &b, void *ws, BatchWs *out) {
     return a.size();
 }
 
+int rows_per_pass(const Plan &P) { return (64 / P.lpr) * (NT / 64); }
+
+// cut every graph into tiles of tile_rows rows (rounded up to whole passes of
+// the step kernel; 0 = four passes) for the slice plan P; the device copies of
+// the tile list and any captured graph are stale afterwards
+void retile(BatchPlan &b, const Plan &P, int tile_rows) {
+    const int rp = rows_per_pass(P);
+    b.P = P;
+    b.tile_rows = tile_rows > 0 ? ((tile_rows + rp - 1) / rp) * rp : rp * 4;
+    b.tiles.clear();
+    b.tile_off.assign(1, 0);
+    for (int q = 0; q < b.G; ++q) {
+        for (int64_t r0 = b.node_off[q]; r0 < b.node_off[q + 1]; r0 += b.tile_rows)
+            b.tiles.push_back(Tile{q, (int32_t)r0, (int32_t)std::min<int64_t>(r0 + b.tile_rows, b.node_off[q + 1]), 0});
+        b.tile_off.push_back((int32_t)b.tiles.size());
+    }
+    b.grid = (int)std::max<size_t>(1, std::min<size_t>(b.tiles.size(), kMaxGrid));
+    b.uploaded_ws = nullptr;
+    if (b.exec) hipGraphExecDestroy(b.exec);
+    if (b.graph) hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+}
+
+asc_status upload_plan(BatchPlan &b, void *ws, hipStream_t s) {
+    BatchWs W;
+    batch_ws_layout(b, ws, &W);
+    ASC_HIP(hipStreamSynchronize(s));
+    ASC_HIP(hipMemcpy(W.tiles, b.tiles.data(), sizeof(Tile) * b.tiles.size(), hipMemcpyHostToDevice));
+    ASC_HIP(hipMemcpy(W.tile_off, b.tile_off.data(), sizeof(int32_t) * b.tile_off.size(), hipMemcpyHostToDevice));
+    ASC_HIP(hipMemcpy(W.k, b.k.data(), sizeof(int32_t) * b.k.size(), hipMemcpyHostToDevice));
+    ASC_HIP(hipMemcpy(W.node_off, b.node_off.data(), sizeof(int64_t) * b.node_off.size(), hipMemcpyHostToDevice));
+    b.uploaded_ws = ws;
+    return ASC_OK;
+}
+
+// the candidates of the batch autotuner: every supported slice width up to
+// the one covering r, times tiles of 1, 2, 4, 8, 16 or 32 passes
+template <typename F>
+void for_each_candidate(const BatchPlan &b, F &&f) {
+    const int vn = vn_of(b.sig);
+    int64_t rcap = 2 * vn;
+    while (rcap < b.r) rcap *= 2;
+    for (int rs = 2 * vn; rs <= 16 * vn && rs <= rcap; rs *= 2) {
+        const Plan P = plan_for(rs, 0u, b.r, b.sig);
+        for (int m = 1; m <= 32; m *= 2) f(P, m * rows_per_pass(P));
+    }
+}
+
 asc_status enqueue_batch(BatchPlan &b, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
                          double *lambda_k, double *traj, void *ws, hipStream_t s) {
     BatchWs W;
@@ -323,18 +372,9 @@ extern "C" asc_status asc_batch_create(const asc_graph *g, int n_graphs, const i
     b->p = p;
     b->steps = steps;
     b->msteps = std::max(1, (p + 1) / 2);
-    b->P = make_plan(g, r, sig);
-    const int rows_pass = (64 / b->P.lpr) * (NT / 64);
-    b->tile_rows = tile_rows > 0 ? ((tile_rows + rows_pass - 1) / rows_pass) * rows_pass : rows_pass * 4;
     b->node_off.assign(node_off_host, node_off_host + n_graphs + 1);
     b->k.assign(k_host, k_host + n_graphs);
-    b->tile_off.push_back(0);
-    for (int q = 0; q < n_graphs; ++q) {
-        for (int64_t r0 = node_off_host[q]; r0 < node_off_host[q + 1]; r0 += b->tile_rows)
-            b->tiles.push_back(Tile{q, (int32_t)r0, (int32_t)std::min<int64_t>(r0 + b->tile_rows, node_off_host[q + 1]), 0});
-        b->tile_off.push_back((int32_t)b->tiles.size());
-    }
-    b->grid = (int)std::max<size_t>(1, std::min<size_t>(b->tiles.size(), kMaxGrid));
+    retile(*b, make_plan(g, r, sig), tile_rows);
     *plan_out = b;
     return ASC_OK;
 }
@@ -353,28 +393,121 @@ extern "C" asc_status asc_batch_info(const void *plan, int *slice_cols, int *til
     return ASC_OK;
 }
 
+namespace asc {
+namespace {
+
+// a copy of the plan's shape only: no captured graph, nothing uploaded
+BatchPlan shape_copy(const BatchPlan &b) {
+    BatchPlan t;
+    t.g = b.g;
+    t.G = b.G;
+    t.r = b.r;
+    t.sig = b.sig;
+    t.p = b.p;
+    t.steps = b.steps;
+    t.msteps = b.msteps;
+    t.P = b.P;
+    t.tile_rows = b.tile_rows;
+    t.node_off = b.node_off;
+    t.k = b.k;
+    t.tiles = b.tiles;
+    t.tile_off = b.tile_off;
+    t.grid = b.grid;
+    return t;
+}
+
+asc_status check_run_args(const BatchPlan &b, const double *lmax, const void *R, int64_t ldr, const float *Y,
+                          int64_t ldy, const double *lambda_k, const double *traj, const char *who) {
+    if (!lmax || !lambda_k || !aligned(lmax, 8) || !aligned(lambda_k, 8) || (traj && !aligned(traj, 8)))
+        return fail(ASC_ERR_INVALID, "%s: lmax/lambda_k NULL or misaligned", who);
+    ASC_TRY(check_block(R, b.sig, b.g.n, b.r, ldr, who, "R"));
+    ASC_TRY(check_block(Y, ASC_F32, b.g.n, b.r, ldy, who, "Y"));
+    return ASC_OK;
+}
+
+}  // namespace
+}  // namespace asc
+
+extern "C" size_t asc_batch_tune_workspace(const void *plan) {
+    if (!plan) return 0;
+    BatchPlan t = shape_copy(*static_cast<const BatchPlan *>(plan));
+    size_t m = 0;
+    for_each_candidate(t, [&](const Plan &P, int tr) {
+        retile(t, P, tr);
+        m = std::max(m, batch_ws_layout(t, nullptr, nullptr));
+    });
+    return m;
+}
+
+extern "C" asc_status asc_batch_autotune(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y,
+                                         int64_t ldy, double *lambda_k, double *traj, int probe_runs, void *ws,
+                                         size_t ws_bytes, int *best_slice_cols, int *best_tile_rows, float *best_ms,
+                                         void *stream) {
+    const char *who = "asc_batch_autotune";
+    if (!plan) return fail(ASC_ERR_INVALID, "%s: NULL plan", who);
+    BatchPlan &b = *static_cast<BatchPlan *>(plan);
+    ASC_TRY(check_run_args(b, lmax, R, ldr, Y, ldy, lambda_k, traj, who));
+    if (probe_runs < 1 || probe_runs > 100) return fail(ASC_ERR_INVALID, "%s: probe_runs=%d", who, probe_runs);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_batch_tune_workspace(plan), who));
+    hipStream_t s = as_stream(stream);
+    // the candidates overwrite the tile lists in ws: whatever b uploaded or
+    // captured there is stale from here on, also if tuning fails
+    retile(b, b.P, b.tile_rows);
+    BatchPlan t = shape_copy(b);
+    hipEvent_t e0, e1;
+    ASC_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(ASC_ERR_HIP, "%s: event creation failed", who);
+    }
+    Plan bestP = b.P;
+    int bestTR = b.tile_rows;
+    float bestMs = 1e30f;
+    bool warm = false;
+    asc_status st = ASC_OK;
+    for_each_candidate(t, [&](const Plan &P, int tr) {
+        if (st != ASC_OK) return;
+        retile(t, P, tr);
+        st = upload_plan(t, ws, s);
+        if (st == ASC_OK && !warm) st = enqueue_batch(t, lmax, R, ldr, Y, ldy, lambda_k, traj, ws, s);
+        warm = true;
+        if (st == ASC_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(ASC_ERR_HIP, "%s: event record", who);
+        for (int it = 0; it < probe_runs && st == ASC_OK; ++it)
+            st = enqueue_batch(t, lmax, R, ldr, Y, ldy, lambda_k, traj, ws, s);
+        if (st != ASC_OK) return;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(ASC_ERR_HIP, "%s: timing failed", who);
+            return;
+        }
+        ms /= (float)probe_runs;
+        if (ms < bestMs) {
+            bestMs = ms;
+            bestP = P;
+            bestTR = t.tile_rows;
+        }
+    });
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != ASC_OK) return st;
+    retile(b, bestP, bestTR);
+    if (best_slice_cols) *best_slice_cols = bestP.rs;
+    if (best_tile_rows) *best_tile_rows = b.tile_rows;
+    if (best_ms) *best_ms = bestMs;
+    return ASC_OK;
+}
+
 extern "C" asc_status asc_batch_run(void *plan, const double *lmax, const void *R, int64_t ldr, float *Y, int64_t ldy,
                                     double *lambda_k, double *traj, void *ws, size_t ws_bytes, int use_graph,
                                     void *stream) {
     const char *who = "asc_batch_run";
     if (!plan) return fail(ASC_ERR_INVALID, "%s: NULL plan", who);
     BatchPlan &b = *static_cast<BatchPlan *>(plan);
-    if (!lmax || !lambda_k || !aligned(lmax, 8) || !aligned(lambda_k, 8) || (traj && !aligned(traj, 8)))
-        return fail(ASC_ERR_INVALID, "%s: lmax/lambda_k NULL or misaligned", who);
-    ASC_TRY(check_block(R, b.sig, b.g.n, b.r, ldr, who, "R"));
-    ASC_TRY(check_block(Y, ASC_F32, b.g.n, b.r, ldy, who, "Y"));
+    ASC_TRY(check_run_args(b, lmax, R, ldr, Y, ldy, lambda_k, traj, who));
     ASC_TRY(check_ws(ws, ws_bytes, asc_batch_workspace(plan), who));
     hipStream_t s = as_stream(stream);
-    if (b.uploaded_ws != ws) {
-        BatchWs W;
-        batch_ws_layout(b, ws, &W);
-        ASC_HIP(hipStreamSynchronize(s));
-        ASC_HIP(hipMemcpy(W.tiles, b.tiles.data(), sizeof(Tile) * b.tiles.size(), hipMemcpyHostToDevice));
-        ASC_HIP(hipMemcpy(W.tile_off, b.tile_off.data(), sizeof(int32_t) * b.tile_off.size(), hipMemcpyHostToDevice));
-        ASC_HIP(hipMemcpy(W.k, b.k.data(), sizeof(int32_t) * b.k.size(), hipMemcpyHostToDevice));
-        ASC_HIP(hipMemcpy(W.node_off, b.node_off.data(), sizeof(int64_t) * b.node_off.size(), hipMemcpyHostToDevice));
-        b.uploaded_ws = ws;
-    }
+    if (b.uploaded_ws != ws) ASC_TRY(upload_plan(b, ws, s));
     if (!use_graph) return enqueue_batch(b, lmax, R, ldr, Y, ldy, lambda_k, traj, ws, s);
     const void *key[8] = {lmax, R, (const void *)(intptr_t)ldr, Y, (const void *)(intptr_t)ldy, lambda_k, traj, ws};
     bool same = b.exec != nullptr;

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1509_08863_amd import _abi
@@ -146,3 +147,33 @@ def test_ari_rejects_before_launch(case):
         wsb = 0
     st = L.asc_ari_pairs(fake, n, ldl, J, k, ari, None, fake, wsb, None)
     assert st == (_abi.ASC_ERR_WORKSPACE if case == "ws_small" else _abi.ASC_ERR_INVALID), case
+
+
+def test_batch_plan_and_tuner_workspace_are_host_only():
+    # a plan over 3 graphs of a fake 1000-node graph: planning, workspace
+    # queries and argument rejection touch no device memory
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x1000)
+    g = _g(1000, 5000)
+    off = np.array([0, 100, 600, 1000], dtype=np.int64)
+    ks = np.array([3, 5, 2], dtype=np.int32)
+    h = ctypes.c_void_p(None)
+    assert L.asc_batch_create(ctypes.byref(g), 3, off.ctypes.data, ks.ctypes.data, 48, 0, 40, 8, 0,
+                              ctypes.byref(h)) == _abi.ASC_OK
+    try:
+        ws = L.asc_batch_workspace(h)
+        tws = L.asc_batch_tune_workspace(h)
+        assert ws > 2 * 1000 * 8 * 4 and tws >= ws
+        # the widest candidate panel (64 float32 columns, two panels) fits
+        assert tws >= 2 * 1000 * 64 * 4
+        a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0.0)
+        for runs, wsb, err in [(0, tws, _abi.ASC_ERR_INVALID), (101, tws, _abi.ASC_ERR_INVALID),
+                               (1, tws - 1, _abi.ASC_ERR_WORKSPACE)]:
+            st = L.asc_batch_autotune(h, fake, fake, 48, fake, 48, fake, None, runs, fake, wsb, ctypes.byref(a),
+                                      ctypes.byref(b), ctypes.byref(c), None)
+            assert st == err, (runs, wsb)
+        assert L.asc_batch_autotune(None, fake, fake, 48, fake, 48, fake, None, 1, fake, tws, None, None, None,
+                                    None) == _abi.ASC_ERR_INVALID
+        assert L.asc_batch_workspace(h) == ws  # rejected calls leave the plan alone
+    finally:
+        assert L.asc_batch_destroy(h) == _abi.ASC_OK

@@ -138,3 +138,60 @@ def test_batch_bf16_runs():
         print(f"bf16 batch graph {q} rel err {err:.3e}")
         assert np.all(np.isfinite(Yh[off[q]:off[q + 1]]))
     B.close()
+
+
+def test_batch_autotuned_plan_matches_oracle_and_replays():
+    # the tuner re-plans (slice width, tile rows); the tuned plan must still
+    # match the oracle per graph, and its captured graph must replay the
+    # eager result exactly
+    gs, big, off, lmaxs, ks = _batch(seed=5)
+    G = upload_graph(big)
+    r, p, steps = 40, 30, 8
+    Rs, R64 = W.signals(big.n, r, 17)
+    ref = _oracle_per_graph(gs, off, lmaxs, ks, R64, p, steps)
+    lm, Rd = to_dev(lmaxs), block_f32(Rs)
+    B = asc.Batch(G, off, ks, r, torch.float32, p, steps)
+    Y = block_f32(np.zeros((big.n, r), np.float32))
+    lam = torch.empty(len(gs), dtype=torch.float64, device=DEV)
+    traj = torch.empty(len(gs), steps, 2, dtype=torch.float64, device=DEV)
+    B.run(lm, Rd, Y, lam, traj, use_graph=True)  # a captured graph exists before tuning
+    best = B.autotune(lm, Rd, Y, lam, traj, probe_runs=1)
+    info = B.info()
+    print("tuned", best, info)
+    assert info["slice_cols"] == best["slice_cols"] and info["tile_rows"] == best["tile_rows"]
+    assert best["slice_cols"] in (8, 16, 32, 64) and best["ms"] > 0
+    Y.zero_()
+    B.run(lm, Rd, Y, lam, traj, use_graph=False)
+    _check(gs, off, ks, host(lam), host(traj), host(Y), ref, 1e-5)
+    eager = [host(Y).copy(), host(lam).copy(), host(traj).copy()]
+    for rep in range(2):
+        Y.zero_()
+        lam.zero_()
+        torch.cuda.synchronize()
+        B.run(lm, Rd, Y, lam, traj, use_graph=True)
+        for a, b in zip([host(Y), host(lam), host(traj)], eager):
+            np.testing.assert_array_equal(a, b)
+    B.close()
+
+
+@pytest.mark.parametrize("rs,tile_rows", [(8, 16), (64, 2048), (16, 10**6)])
+def test_batch_extreme_tilings_match_oracle(rs, tile_rows):
+    # the ends of the tuner's range: the narrowest and widest slices, one-pass
+    # tiles and tiles longer than every graph (one tile per graph)
+    gs, big, off, lmaxs, ks = _batch(seed=6)
+    G = upload_graph(big)
+    r, p, steps = 40, 24, 8
+    asc.tune_set(G, r, torch.float32, rs, 0)
+    try:
+        B = asc.Batch(G, off, ks, r, torch.float32, p, steps, tile_rows=tile_rows)
+    finally:
+        asc.tune_set(G, r, torch.float32, 0, 0)
+    assert B.info()["slice_cols"] == rs
+    Rs, R64 = W.signals(big.n, r, 23)
+    ref = _oracle_per_graph(gs, off, lmaxs, ks, R64, p, steps)
+    Y = block_f32(np.zeros((big.n, r), np.float32))
+    lam = torch.empty(len(gs), dtype=torch.float64, device=DEV)
+    traj = torch.empty(len(gs), steps, 2, dtype=torch.float64, device=DEV)
+    B.run(to_dev(lmaxs), block_f32(Rs), Y, lam, traj, use_graph=True)
+    _check(gs, off, ks, host(lam), host(traj), host(Y), ref, 1e-5)
+    B.close()
