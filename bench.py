@@ -83,6 +83,11 @@ def _time(fn, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
+def _progress(msg):
+    """One line per finished phase on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def extra_knn(dev):
     """Gaussian-mixture 10-NN graph, N = 2e5, R = 64, p = 100: lambda_k + filter
     in one pass, forward+backward through the autograd wrappers (sigma, weights,
@@ -287,10 +292,21 @@ def extra_mid(dev):
     ms = _time(lambda: asc.cheb_filter(G, lmax, a, R, Y), 10)
     gbs = p * b_step(g.n, g.nnz, r, 4) / (ms * 1e-3) / 1e9
     llc = copy_bandwidth(dev, 64 << 20, 50)["GBps"]
+    # lambda_k by dichotomy (12 steps): one moment pass, or one filter pass
+    # (without Y) per trial cut-off
+    k, steps = cfg["k"], cfg["steps"]
+    ms_mom = _time(lambda: asc.eigcount_lambda_k(G, lmax, k, p, steps, R), 5)
+    ms_lit = _time(lambda: asc.eigcount_lambda_k(G, lmax, k, p, steps, R, literal=True), 2)
+    lam_m, traj_m = asc.eigcount_lambda_k(G, lmax, k, p, steps, R)
+    lam_l, traj_l = asc.eigcount_lambda_k(G, lmax, k, p, steps, R, literal=True)
+    same = bool(torch.equal(traj_m[:, 0], traj_l[:, 0]))
     return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ms_per_filter_fwd": round(ms, 3),
             "gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
             "copy_gbs_64MiB": round(llc, 1), "frac_of_cache_resident_copy": round(gbs / llc, 4),
-            "tuned": {"slice_cols": tuned[0], "variant": tuned[1]}}
+            "tuned": {"slice_cols": tuned[0], "variant": tuned[1]},
+            "lambda_k": {"k": k, "steps": steps, "ms_moments": round(ms_mom, 3), "ms_literal": round(ms_lit, 3),
+                         "estimate_moments": float(lam_m.cpu()[0]), "estimate_literal": float(lam_l.cpu()[0]),
+                         "same_trajectory": same}}
 
 
 def extra_knn_build(dev, n=200_000, d=16, k=10):
@@ -370,6 +386,7 @@ def main():
     seeds = W.config_seeds(args.config)
     t0 = time.time()
     g = W.config_graph(args.config)
+    _progress(f"graph {cfg['name']}: n={g.n} nnz={g.nnz}")
     n, nnz, r, p, k = g.n, g.nnz, cfg["r"], cfg["p"], cfg["k"]
     steps_dich, km_iters = cfg["steps"], cfg["kmeans_iters"]
     R32, R64 = W.signals(n, r, seeds["signals"])
@@ -429,6 +446,7 @@ def main():
             rec.append(marks)
         return lmax, lam_k, lab
 
+    _progress(f"tuned {tuned}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -448,20 +466,26 @@ def main():
     lam_k_h = float(out[1].cpu()[0])
 
     # filter alone (fp32 and bf16), events on the launch stream
-    def time_filter(Rin, reps=5):
+    # 3 warm-up filters, then 20 back-to-back filters with an event between
+    # each: mean (the reported rate), median and min per filter
+    def time_filter(Rin, reps=20, warm=3):
         a = asc.cheb_coeffs(out[1], out[0], p)
-        asc.cheb_filter(G, out[0], a, Rin, Y)
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        e0.record()
-        for _ in range(reps):
+        for _ in range(warm):
             asc.cheb_filter(G, out[0], a, Rin, Y)
-        e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        es = [ev() for _ in range(reps + 1)]
+        es[0].record()
+        for q in range(reps):
+            asc.cheb_filter(G, out[0], a, Rin, Y)
+            es[q + 1].record()
+        torch.cuda.synchronize()
+        each = [es[q].elapsed_time(es[q + 1]) for q in range(reps)]
+        return float(np.mean(each)), {"median": round(float(np.median(each)), 4), "min": round(min(each), 4),
+                                      "reps": reps}
 
-    ms_f32 = time_filter(R)
-    ms_bf16 = None if args.no_bf16 else time_filter(Rb)
+    _progress(f"{args.steps} pipeline steps: {ms_step:.1f} ms/step")
+    ms_f32, stats_f32 = time_filter(R)
+    ms_bf16, stats_bf16 = (None, None) if args.no_bf16 else time_filter(Rb)
     # pattern-only graph (w = NULL: unit weights, no weight stream), same plan
     ms_pat = None
     if not args.no_pattern:
@@ -493,6 +517,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_fb = e0.elapsed_time(e1) / reps
+        _progress(f"filter {ms_f32:.1f} ms, fwd+bwd {ms_fb:.1f} ms")
     bs32 = b_step(n, nnz, r, 4)
     bs16 = b_step(n, nnz, r, 2)
     bs_pat = b_step(n, nnz, r, 4, weighted=False)
@@ -558,10 +583,14 @@ def main():
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     extra = None
     if args.extra:
-        extra = {"small": extra_small(dev), "mid": extra_mid(dev), "knn_grad": extra_knn(dev), "batch": extra_batch(dev),
-                 "knn_build": extra_knn_build(dev),
-                 "stability": extra_stability(dev, 6),
-                 "stability_large": extra_stability(dev, 7, 1)}
+        parts = [("small", lambda: extra_small(dev)), ("mid", lambda: extra_mid(dev)),
+                 ("knn_grad", lambda: extra_knn(dev)), ("batch", lambda: extra_batch(dev)),
+                 ("knn_build", lambda: extra_knn_build(dev)), ("stability", lambda: extra_stability(dev, 6)),
+                 ("stability_large", lambda: extra_stability(dev, 7, 1))]
+        extra = {}
+        for name, fn in parts:
+            extra[name] = fn()
+            _progress(f"extra {name} done")
     line = {
         "metric": "Chebyshev-filter SpMM HBM GB/s + ms/filter (fwd, fwd+bwd) at err vs FP64",
         "value": round(gbs32, 2),
@@ -578,10 +607,12 @@ def main():
         "config": {"workload": cfg["name"], "n": n, "nnz": nnz, "r": r, "p": p, "k": k,
                    "dichotomy_steps": steps_dich, "kmeans_iters": km_iters},
         "ms_per_filter_fwd": round(ms_f32, 4),
+        "ms_per_filter_fwd_stats": stats_f32,
         "ms_per_filter_fwd_bwd": None if ms_fb is None else round(ms_fb, 4),
         "tuned": {k_: {"slice_cols": v[0], "variant": v[1], "ms_per_step": round(v[2], 4)} for k_, v in tuned.items()},
         "err_vs_fp64": err,
-        "bf16": None if ms_bf16 is None else {"ms_per_filter_fwd": round(ms_bf16, 4), "gbs": round(gbs16, 2)},
+        "bf16": None if ms_bf16 is None else {"ms_per_filter_fwd": round(ms_bf16, 4), "gbs": round(gbs16, 2),
+                                              "ms_per_filter_fwd_stats": stats_bf16},
         "components_ms": {k_: round(v, 4) for k_, v in comp.items()},
         "lambda_max": lmax_h,
         "lambda_k_est": lam_k_h,
