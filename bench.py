@@ -52,7 +52,7 @@ STEP_TRAFFIC = {
 def step_kernel_sha1():
     import hashlib
     src = open(os.path.join(ROOT, "paper_1509_08863_amd", "csrc", "recurrence.hpp")).read()
-    a = src.index("// One row of a recurrence step")
+    a = src.index("// The rest of a row's step for one panel")
     b = src.index("// d_i = 4 s_i / lmax - 2")
     return hashlib.sha1(src[a:b].encode()).hexdigest()
 
@@ -189,6 +189,19 @@ def copy_bandwidth(dev, nbytes, reps):
     ms = _time(lambda: asc.stream_copy(src, dst), reps)
     del src, dst
     return {"copy_bytes_per_launch": 2 * nbytes, "ms": ms, "GBps": 2 * nbytes / ms / 1e6}
+
+
+def gather_floor_ms(dev, col_idx, n, reps=20):
+    """Time of gathering one 128-byte row per stored entry, in the graph's own
+    column-index order, from an n x 32 float32 table: the neighbour-gather
+    floor of one 32-column recurrence step."""
+    import torch
+    import paper_1509_08863_amd as asc
+    table = torch.zeros(n, 32, dtype=torch.float32, device=dev)
+    sink = torch.zeros(1, dtype=torch.float32, device=dev)
+    ms = _time(lambda: asc.gather_probe(table, col_idx, sink), reps)
+    del table
+    return ms
 
 
 def extra_stability(dev, c=6, reps_timed=3):
@@ -353,6 +366,8 @@ def parse():
     ap.add_argument("--knn-grad-only", action="store_true", help="only time the kNN-gradient workload and exit")
     ap.add_argument("--stability-only", type=int, default=0, metavar="C",
                     help="only time the stability sweep of configuration C (6 or 7) and exit")
+    ap.add_argument("--filter-only", action="store_true",
+                    help="only run float32 filters of the headline graph (counter runs) and exit")
     ap.add_argument("--tune", default=None, metavar="RS,VAR",
                     help="fixed float32 launch configuration (slice columns, variant) instead of the autotuner")
     return ap.parse_args()
@@ -416,6 +431,16 @@ def main():
     if not args.no_tune and not args.no_bf16:
         lm0 = asc.lmax_estimate(G, v0d, 60)
         tuned["bf16"] = asc.autotune_filter(G, lm0, Rb, 2)
+
+    if args.filter_only:
+        # the filter alone at lambda_c = 0.17 lambda_max (2 untimed + 3 timed)
+        lm = asc.lmax_estimate(G, v0d, 60)
+        a = asc.cheb_coeffs(lm * 0.17, lm, p)
+        for _ in range(2):
+            asc.cheb_filter(G, lm, a, R, Y)
+        ms = _time(lambda: asc.cheb_filter(G, lm, a, R, Y), 3)
+        print(json.dumps({"workload": cfg["name"], "ms_per_filter_fwd": round(ms, 4), "tuned": tuned.get("f32")}))
+        return
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     comp_names = ["prepare", "lmax", "lambda_k_coeffs_filter", "-", "-", "normalize", "kmeans"]
@@ -581,6 +606,7 @@ def main():
     traffic = step_traffic_bytes(cfg["name"], rs32, var32)
     copy_big = copy_bandwidth(dev, 2 << 30, 10)
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
+    gfloor = gather_floor_ms(dev, ci, n) if rs32 == 32 else None
     extra = None
     if args.extra:
         parts = [("small", lambda: extra_small(dev)), ("mid", lambda: extra_mid(dev)),
@@ -628,7 +654,9 @@ def main():
                      "amplification": None if traffic is None else round(traffic / alg_launch, 3),
                      "traffic_gbs": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 1),
                      "copy_gbs_2GiB": round(copy_big["GBps"], 1), "copy_gbs_64MiB": round(copy_llc["GBps"], 1),
-                     "frac_of_copy": round(alg_launch / (launch_ms * 1e-3) / 1e9 / (copy_big["GBps"]), 4)},
+                     "frac_of_copy": round(alg_launch / (launch_ms * 1e-3) / 1e9 / (copy_big["GBps"]), 4),
+                     "gather_floor_ms": None if gfloor is None else round(gfloor, 5),
+                     "frac_of_gather_floor": None if gfloor is None else round(gfloor / launch_ms, 4)},
         "cpu_baseline": cpu,
         "extra": extra,
         "gen_s": round(gen_s, 1),

@@ -392,7 +392,15 @@ asc_status asc_ari_pairs(const int32_t *labels, int64_t n, int64_t ldl, int J, i
  *               with one coalesced request and broadcast them in the row
  *               group (fewer vector-memory requests per neighbour); bit 2:
  *               each XCD processes one contiguous band of rows (L2 locality
- *               for graphs whose neighbours are close in index order).
+ *               for graphs whose neighbours are close in index order); bit 3
+ *               (slice widths of 8 lanes per row, i.e. 32 float32 or 64
+ *               bfloat16 columns, and 2 to 4 slices): one launch per step
+ *               covers every slice, reading the row's column indices and
+ *               weights once (it gathers all slices' panels at once, so it
+ *               pays where they fit the Infinity Cache together); with bit 3
+ *               only bit 2 of the others applies.  0 <= variant <= 15.
+ * Every filter step writes T_{j+1}; Y is read and updated on every other step
+ * (a_j T_j + a_{j+1} T_{j+1} together) and on the last one.
  * asc_autotune_filter times every candidate on the caller's graph and signals
  * for probe_steps recurrence steps (Y and ws are scratch; needs ws of
  * asc_filter_workspace(n, r, sig, 1) bytes), records the fastest and returns
@@ -411,6 +419,16 @@ asc_status asc_autotune_filter(const asc_graph *g, const double *lmax, const voi
  * aligned pointers): the reference kernel for measured copy bandwidth and for
  * calibrating memory counters. */
 asc_status asc_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* Random-row gather reference: reads row idx[e] (clamped into [0, rows)) of
+ * a table of `rows` rows of 32 float32 (128 bytes, 16-byte aligned) for every
+ * e < nidx, with the recurrence's access shape (8 lanes of 16 bytes per row,
+ * 8 rows in flight per lane group).  Driven by a graph's column indices, its
+ * time is the floor that the neighbour gathers of one 32-column recurrence
+ * step set on this device.  sink[0] (device) is written only if a lane's sum
+ * equals 1.2345678e7. */
+asc_status asc_gather_probe(const float *table, int64_t rows, const int32_t *idx, int64_t nidx, float *sink,
+                            void *stream);
 
 /* Health flags raised by the last filter / moment pass that used ws.
  * Synchronises the stream; flags_host gets ASC_FLAG_* bits.  Returns

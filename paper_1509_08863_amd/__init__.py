@@ -475,6 +475,14 @@ def ari_pairs(labels: torch.Tensor, k: int):
     return ari, mean
 
 
+def gather_probe(table: torch.Tensor, idx: torch.Tensor, sink: torch.Tensor) -> None:
+    """Reads rows idx[e] of a (rows x 32) float32 table (asc_gather_probe)."""
+    assert table.dtype == torch.float32 and table.dim() == 2 and table.shape[1] == 32 and table.is_contiguous()
+    assert idx.dtype == torch.int32 and idx.is_contiguous()
+    _abi.check(_abi.lib().asc_gather_probe(_ptr(table), table.shape[0], _ptr(idx), idx.numel(), _ptr(sink),
+                                           _stream()))
+
+
 def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     """dst <- src (same byte size), plain 16-byte streaming copy kernel."""
     nb = src.numel() * src.element_size()

@@ -68,6 +68,7 @@ SIGNATURES = {
     "asc_kmeans_update_workspace": (SZ, [I64, I64, I32]),
     "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
     "asc_stream_copy": (I32, [P, P, SZ, P]),
+    "asc_gather_probe": (I32, [P, I64, P, I64, P, P]),
     "asc_read_flags": (I32, [P, ctypes.POINTER(ctypes.c_uint32), P]),
     "asc_gauss_weights": (I32, [P, I64, D, P, P]),
     "asc_gauss_weights_bwd_workspace": (SZ, [I64]),

@@ -47,7 +47,9 @@ __global__ __launch_bounds__(NT) void batch_step(BatchArgs B) {
         const float beta = B.betas[T.g];
         const double *a = B.coeffs + (int64_t)T.g * B.p1;
         const float aj1 = (MODE & M_YACC) ? (float)a[B.S.j + 1] : 0.0f;
-        const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)a[0] : 0.0f;
+        const float a0 = !(MODE & M_YACC) ? 0.0f
+                         : (MODE & M_FIRST) ? (float)a[0]
+                         : (MODE & M_YPAIR) ? (float)a[B.S.j] : 0.0f;
         double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
         for (int64_t r0 = T.r0; r0 < T.r1; r0 += ROWS) {
             const int64_t row = r0 + (int64_t)wave * RPW + sub;
@@ -73,6 +75,8 @@ hipError_t launch_batch_t(unsigned mode, const BatchArgs &B, int grid, hipStream
         case M_PART: batch_step<TS, LPR, M_PART><<<grid, NT, 0, s>>>(B); break;
         case M_FIRST | M_YACC: batch_step<TS, LPR, M_FIRST | M_YACC><<<grid, NT, 0, s>>>(B); break;
         case M_YACC: batch_step<TS, LPR, M_YACC><<<grid, NT, 0, s>>>(B); break;
+        case M_YACC | M_YPAIR: batch_step<TS, LPR, M_YACC | M_YPAIR><<<grid, NT, 0, s>>>(B); break;
+        case 0u: batch_step<TS, LPR, 0u><<<grid, NT, 0, s>>>(B); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -333,7 +337,7 @@ asc_status enqueue_batch(BatchPlan &b, const double *lmax, const void *R, int64_
             B.S.prev = j == 0 ? nullptr : prev;
             B.S.out = prev;
             B.S.j = j;
-            hipError_t e = launch_batch(b.sig, b.P.lpr, (j == 0 ? M_FIRST : 0u) | M_YACC, B, b.grid, s);
+            hipError_t e = launch_batch(b.sig, b.P.lpr, j == 0 ? (M_FIRST | M_YACC) : y_mode(j, b.p), B, b.grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "batch_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
         }

@@ -51,6 +51,45 @@ bool tuned(int64_t n, int64_t nnz, int64_t r, asc_dtype dt, TuneEntry *out) {
 
 
 // ---------------------------------------------------------------------------
+// launches of a plan: one slice per launch, or every slice in one launch
+// (variant bit 3; 8 lanes per row, 2 to 4 slices; of the other bits only the
+// XCD-band schedule applies there)
+// ---------------------------------------------------------------------------
+template <typename TS>
+hipError_t launch_np_t(unsigned var, int np, unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
+    const bool bands = (var & 4u) != 0;
+    switch (np) {
+        case 2: return bands ? launch_step_v<TS, 8, 4u, 2>(mode, A, grid, s) : launch_step_v<TS, 8, 0u, 2>(mode, A, grid, s);
+        case 3: return bands ? launch_step_v<TS, 8, 4u, 3>(mode, A, grid, s) : launch_step_v<TS, 8, 0u, 3>(mode, A, grid, s);
+        case 4: return bands ? launch_step_v<TS, 8, 4u, 4>(mode, A, grid, s) : launch_step_v<TS, 8, 0u, 4>(mode, A, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plan(const Plan &P, asc_dtype dt, unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
+    if (P.np > 1)
+        return dt == ASC_F32 ? launch_np_t<float>(P.var, P.np, mode, A, grid, s)
+                             : launch_np_t<uint16_t>(P.var, P.np, mode, A, grid, s);
+    return launch_step(dt, P.lpr, P.var, mode, A, grid, s);
+}
+
+// R columns c0 .. c0 + np*rs - 1 into np consecutive panels `pstride` elements apart
+void pack_panels(const Plan &P, int64_t n, const void *R, asc_dtype sig, int64_t ldr, int64_t r, int sl0, void *dst,
+                 int64_t pstride, hipStream_t s) {
+    const int64_t tot = n * P.rs;
+    const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+    for (int q = 0; q < P.np; ++q) {
+        const int64_t c0 = (int64_t)(sl0 + q) * P.rs;
+        if (sig == ASC_F32)
+            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs,
+                                                  static_cast<float *>(dst) + q * pstride);
+        else
+            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs,
+                                                     static_cast<uint16_t *>(dst) + q * pstride);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the filter, shared by asc_cheb_filter and the literal eigencount
 // ---------------------------------------------------------------------------
 asc_status run_filter(const asc_graph *g, const double *lmax, const double *coeffs, int p, const void *R,
@@ -87,20 +126,17 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
     auto slot = [&](int sl, int j) -> void * {
         return static_cast<char *>(ckpt) + ((size_t)sl * (p + 1) + j) * pbytes;
     };
-    for (int sl = 0; sl < P.nslices; ++sl) {
+    // panels of the slices of one launch: consecutive panels of the ping-pong
+    // buffers, or the slots of consecutive slices in the state store
+    const int64_t pstride = (int64_t)((store_all ? (size_t)(p + 1) * pbytes : pbytes) / esize(sig));
+    for (int sl = 0; sl < P.nslices; sl += P.np) {
         const int64_t c0 = (int64_t)sl * P.rs;
         void *pa = store_all ? slot(sl, 0) : F.panelA;
         void *pb = store_all ? slot(sl, 1) : F.panelB;
-        {
-            const int64_t tot = n * P.rs;
-            const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-            if (sig == ASC_F32)
-                pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)pa);
-            else
-                pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)pa);
-            ASC_LAUNCHED();
-        }
+        pack_panels(P, n, R, sig, ldr, r, sl, pa, pstride, s);
+        ASC_LAUNCHED();
         StepArgs A{};
+        A.pstride = pstride;
         A.n = n;
         A.rp = g->row_ptr;
         A.ci = g->col_idx;
@@ -121,7 +157,7 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
         A.ck_ld = ck_ld_of(r, sig);
         A.ck_a = ckb ? ck_block(0, 0) : nullptr;
         A.ck_b = ckb ? ck_block(0, 1) : nullptr;
-        hipError_t e = launch_step(sig, P.lpr, P.var, M_FIRST | M_YACC | M_PART, A, grid, s);
+        hipError_t e = launch_plan(P, sig, M_FIRST | M_YACC | M_PART, A, grid, s);
         if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
         sum_partials_kernel<<<1, NT, 0, s>>>(grid, F.part, 1, 0, F.first);
         ASC_LAUNCHED();
@@ -136,7 +172,7 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
             const bool ck = ckb && (j % ckpt_stride == 0);
             A.ck_a = ck ? ck_block(j / ckpt_stride, 0) : nullptr;
             A.ck_b = ck ? ck_block(j / ckpt_stride, 1) : nullptr;
-            e = launch_step(sig, P.lpr, P.var, M_YACC | (last ? M_PART : 0u), A, grid, s);
+            e = launch_plan(P, sig, y_mode(j, p) | (last ? M_PART : 0u), A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
         }
@@ -164,16 +200,13 @@ asc_status run_moments(const asc_graph *g, const double *lmax, int p, const void
     diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, g->strength, lmax, F.diag, F.beta, flags, 1);
     ASC_LAUNCHED();
     const int grid = grid_for(n, P.lpr);
-    for (int sl = 0; sl < P.nslices; ++sl) {
-        const int64_t c0 = (int64_t)sl * P.rs;
-        const int64_t tot = n * P.rs;
-        const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-        if (sig == ASC_F32)
-            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)F.panelA);
-        else
-            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)F.panelA);
+    const int64_t pstride = (int64_t)(panel_bytes(n, P.rs, sig) / esize(sig));
+    int groups = 0;
+    for (int sl = 0; sl < P.nslices; sl += P.np, ++groups) {
+        pack_panels(P, n, R, sig, ldr, r, sl, F.panelA, pstride, s);
         ASC_LAUNCHED();
         StepArgs A{};
+        A.pstride = pstride;
         A.n = n;
         A.rp = g->row_ptr;
         A.ci = g->col_idx;
@@ -188,15 +221,15 @@ asc_status run_moments(const asc_graph *g, const double *lmax, int p, const void
             A.out = prev;
             A.j = st;
             A.partials = F.part + (int64_t)st * kMaxGrid * 3;
-            hipError_t e = launch_step(sig, P.lpr, P.var, (st == 0 ? M_FIRST : 0u) | M_PART, A, grid, s);
+            hipError_t e = launch_plan(P, sig, (st == 0 ? M_FIRST : 0u) | M_PART, A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
         }
         sum_partials_kernel<<<steps, NT, 0, s>>>(grid, F.part, steps, (int64_t)kMaxGrid * 3,
-                                                 F.sums + (int64_t)sl * steps * 3);
+                                                 F.sums + (int64_t)groups * steps * 3);
         ASC_LAUNCHED();
     }
-    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, P.nslices, steps, p, mu, flags);
+    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, groups, steps, p, mu, flags);
     ASC_LAUNCHED();
     return ASC_OK;
 }
@@ -486,19 +519,17 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
     bestE.ms = 1e30f;
     asc_status st = ASC_OK;
     for (int rs = 2 * vn; rs <= 16 * vn && rs <= rcap; rs *= 2) {
-        for (unsigned var = 0; var < 8; ++var) {
+        for (unsigned var = 0; var < 16; ++var) {
             const Plan P = plan_for(rs, var, r, sig);
+            // bit 3 only where one launch can cover every slice, and then
+            // only with the tile-schedule bit
+            if ((var & 8u) != 0 && (P.np == 1 || (var & 3u) != 0)) continue;
             const int grid = grid_for(n, P.lpr);
-            const int64_t tot = n * P.rs;
-            const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-            for (void *panel : {F.panelA, F.panelB}) {
-                if (sig == ASC_F32)
-                    pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, 0, r, P.rs, (float *)panel);
-                else
-                    pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, 0, r, P.rs,
-                                                             (uint16_t *)panel);
-            }
+            const int64_t pstride = (int64_t)(panel_bytes(n, P.rs, sig) / esize(sig));
+            for (void *panel : {F.panelA, F.panelB}) pack_panels(P, n, R, sig, ldr, r, 0, panel, pstride, s);
+            ASC_LAUNCHED();
             StepArgs A{};
+            A.pstride = pstride;
             A.n = n;
             A.rp = g->row_ptr;
             A.ci = g->col_idx;
@@ -512,26 +543,30 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
             A.j = 0;
             void *cur = F.panelA, *prev = F.panelB;
             float ms = 0.f;
-            for (int it = -1; it < probe_steps; ++it) {
+            // steps in pairs, as the filter runs them: one that adds a pair of
+            // terms to Y, one that leaves Y alone
+            for (int it = -1; it < probe_steps && st == ASC_OK; ++it) {
                 if (it == 0) (void)hipEventRecord(e0, s);
-                for (int sl = 0; sl < P.nslices; ++sl) {
-                    A.c0 = (int64_t)sl * P.rs;
-                    A.cur = cur;
-                    A.prev = prev;
-                    A.out = prev;
-                    hipError_t e = launch_step(sig, P.lpr, P.var, M_YACC, A, grid, s);
-                    if (e != hipSuccess) {
-                        st = fail(ASC_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(e));
-                        break;
+                for (int half = 0; half < 2 && st == ASC_OK; ++half) {
+                    for (int sl = 0; sl < P.nslices; sl += P.np) {
+                        A.c0 = (int64_t)sl * P.rs;
+                        A.cur = cur;
+                        A.prev = prev;
+                        A.out = prev;
+                        hipError_t e = launch_plan(P, sig, half == 0 ? (M_YACC | M_YPAIR) : 0u, A, grid, s);
+                        if (e != hipSuccess) {
+                            st = fail(ASC_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(e));
+                            break;
+                        }
                     }
+                    std::swap(cur, prev);
                 }
-                std::swap(cur, prev);
             }
             if (st != ASC_OK) break;
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= (float)std::max(1, probe_steps);
+            ms /= (float)(2 * std::max(1, probe_steps));
             if (ms < bestE.ms) {
                 bestE.ms = ms;
                 bestE.rs = rs;
@@ -564,7 +599,7 @@ extern "C" asc_status asc_tune_set(int64_t n, int64_t nnz, int64_t r, asc_dtype 
     if (sig != ASC_F32 && sig != ASC_BF16) return fail(ASC_ERR_INVALID, "asc_tune_set: dtype");
     if (slice_cols != 0 && !valid_rs(slice_cols, sig))
         return fail(ASC_ERR_INVALID, "asc_tune_set: slice_cols=%d not supported for this dtype", slice_cols);
-    if (variant < 0 || variant > 7) return fail(ASC_ERR_INVALID, "asc_tune_set: variant=%d", variant);
+    if (variant < 0 || variant > 15) return fail(ASC_ERR_INVALID, "asc_tune_set: variant=%d", variant);
     std::lock_guard<std::mutex> lk(tune_mutex());
     auto &t = tune_table();
     const TuneKey key{n, nnz, r, (int)sig};
@@ -620,7 +655,7 @@ extern "C" asc_status asc_tune_load(const char *path) {
         double ms;
         if (sscanf(line, " {\"n\": %lld, \"nnz\": %lld, \"r\": %lld, \"dtype\": %d, \"slice_cols\": %d, \"variant\": %d, \"ms\": %lf",
                    &n, &nnz, &r, &dt, &rs, &var, &ms) == 7) {
-            if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && var >= 0 && var <= 7) {
+            if ((dt == 0 || dt == 1) && valid_rs(rs, (asc_dtype)dt) && var >= 0 && var <= 15) {
                 asc_tune_set(n, nnz, r, (asc_dtype)dt, rs, var);
             }
         }
@@ -671,16 +706,12 @@ asc_status run_store(const asc_graph *g, const double *lmax, int p, const void *
     const int grid = grid_for(n, P.lpr);
     const size_t pbytes = panel_bytes(n, P.rs, sig);
     auto slot = [&](int sl, int j) -> void * { return static_cast<char *>(states) + ((size_t)sl * (p + 1) + j) * pbytes; };
-    const int64_t tot = n * P.rs;
-    const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    for (int sl = 0; sl < P.nslices; ++sl) {
-        const int64_t c0 = (int64_t)sl * P.rs;
-        if (sig == ASC_F32)
-            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)slot(sl, 0));
-        else
-            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)slot(sl, 0));
+    const int64_t pstride = (int64_t)((size_t)(p + 1) * pbytes / esize(sig));
+    for (int sl = 0; sl < P.nslices; sl += P.np) {
+        pack_panels(P, n, R, sig, ldr, r, sl, slot(sl, 0), pstride, s);
         ASC_LAUNCHED();
         StepArgs A{};
+        A.pstride = pstride;
         A.n = n;
         A.rp = g->row_ptr;
         A.ci = g->col_idx;
@@ -692,7 +723,7 @@ asc_status run_store(const asc_graph *g, const double *lmax, int p, const void *
             A.prev = j == 0 ? nullptr : slot(sl, j - 1);
             A.out = slot(sl, j + 1);
             A.j = j;
-            hipError_t e = launch_step(sig, P.lpr, P.var, j == 0 ? M_FIRST : 0u, A, grid, s);
+            hipError_t e = launch_plan(P, sig, j == 0 ? M_FIRST : 0u, A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
         }
     }
@@ -786,16 +817,13 @@ extern "C" asc_status asc_lambda_k_filter(const asc_graph *g, const double *lmax
     const int grid = grid_for(n, P.lpr);
     const size_t pbytes = panel_bytes(n, P.rs, sig);
     auto slot = [&](int sl, int j) -> void * { return static_cast<char *>(states) + ((size_t)sl * (p + 1) + j) * pbytes; };
-    const int64_t tot = n * P.rs;
-    const int pg = (int)std::min<int64_t>((tot + 255) / 256, 65536);
-    for (int sl = 0; sl < P.nslices; ++sl) {
-        const int64_t c0 = (int64_t)sl * P.rs;
-        if (sig == ASC_F32)
-            pack_kernel<float><<<pg, 256, 0, s>>>(n, (const float *)R, ldr, c0, r, P.rs, (float *)slot(sl, 0));
-        else
-            pack_kernel<uint16_t><<<pg, 256, 0, s>>>(n, (const uint16_t *)R, ldr, c0, r, P.rs, (uint16_t *)slot(sl, 0));
+    const int64_t pstride = (int64_t)((size_t)(p + 1) * pbytes / esize(sig));
+    int groups = 0;
+    for (int sl = 0; sl < P.nslices; sl += P.np, ++groups) {
+        pack_panels(P, n, R, sig, ldr, r, sl, slot(sl, 0), pstride, s);
         ASC_LAUNCHED();
         StepArgs A{};
+        A.pstride = pstride;
         A.n = n;
         A.rp = g->row_ptr;
         A.ci = g->col_idx;
@@ -809,14 +837,14 @@ extern "C" asc_status asc_lambda_k_filter(const asc_graph *g, const double *lmax
             A.j = j;
             const bool part = j < msteps;
             A.partials = part ? F.part + (int64_t)j * kMaxGrid * 3 : nullptr;
-            hipError_t e = launch_step(sig, P.lpr, P.var, (j == 0 ? M_FIRST : 0u) | (part ? M_PART : 0u), A, grid, s);
+            hipError_t e = launch_plan(P, sig, (j == 0 ? M_FIRST : 0u) | (part ? M_PART : 0u), A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
         }
         sum_partials_kernel<<<msteps, NT, 0, s>>>(grid, F.part, msteps, (int64_t)kMaxGrid * 3,
-                                                  F.sums + (int64_t)sl * msteps * 3);
+                                                  F.sums + (int64_t)groups * msteps * 3);
         ASC_LAUNCHED();
     }
-    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, P.nslices, msteps, p, mu, flags);
+    moments_finalize_kernel<<<1, 64, 0, s>>>(F.sums, groups, msteps, p, mu, flags);
     ASC_LAUNCHED();
     dichotomy_kernel<<<1, NT, 0, s>>>(mu, p, lmax, k, steps, 1, lambda_k, traj);
     ASC_LAUNCHED();

@@ -84,7 +84,53 @@ __global__ void stream_copy_kernel(const uint4 *__restrict__ src, uint4 *__restr
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
 }
+// rows idx[e] of a table of 128-byte rows: 8 lanes per row (16 bytes each),
+// 8 rows in flight per lane group, grid-stride over the index list; indices
+// are clamped into the table; a lane writes its sum to sink[0] only when it
+// equals a fixed sentinel, which keeps the loads live
+__global__ __launch_bounds__(256) void gather_probe_kernel(const float4 *__restrict__ table, int64_t rows,
+                                                           const int32_t *__restrict__ idx, int64_t nidx,
+                                                           float *__restrict__ sink) {
+    constexpr int LPR = 8, U = 8;
+    const int t = threadIdx.x % LPR;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / LPR;
+    float a = 0.0f, b = 0.0f, c = 0.0f, d = 0.0f;
+    for (int64_t e = grp * U; e < nidx; e += ngrp * U) {
+        int64_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t kk = e + u < nidx ? (int64_t)idx[e + u] : 0;
+            k[u] = kk < 0 ? 0 : (kk >= rows ? rows - 1 : kk);
+        }
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = table[k[u] * LPR + t];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a += v[u].x;
+            b += v[u].y;
+            c += v[u].z;
+            d += v[u].w;
+        }
+    }
+    const float s = a + b + c + d;
+    if (s == 1.2345678e7f) sink[0] = s;
+}
 }  // namespace
+
+extern "C" asc_status asc_gather_probe(const float *table, int64_t rows, const int32_t *idx, int64_t nidx,
+                                       float *sink, void *stream) {
+    if (!table || !idx || !sink || rows < 1 || nidx < 0 || !aligned(table, 16) || !aligned(idx, 4))
+        return fail(ASC_ERR_INVALID, "asc_gather_probe: NULL or misaligned pointer, or rows < 1");
+    if (nidx == 0) return ASC_OK;
+    const int64_t groups = (nidx + 7) / 8;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((groups * 8 + 255) / 256, 256 * 32));
+    gather_probe_kernel<<<grid, 256, 0, as_stream(stream)>>>(reinterpret_cast<const float4 *>(table), rows, idx,
+                                                              nidx, sink);
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
 
 extern "C" asc_status asc_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
     if (!src || !dst || bytes % 16 || !aligned(src, 16) || !aligned(dst, 16))

@@ -30,6 +30,7 @@ constexpr int kMaxGrid = 8192;   // cap of blocks per step launch (grid-stride b
 constexpr unsigned M_FIRST = 1u;  // step 0: T_1 = Lt T_0 (there is no T_{-1})
 constexpr unsigned M_YACC = 2u;   // Y += a_{j+1} T_{j+1}; with M_FIRST: Y = a_0 T_0 + a_1 T_1
 constexpr unsigned M_PART = 4u;   // write float64 partial sums
+constexpr unsigned M_YPAIR = 8u;  // with M_YACC: Y += a_j T_j + a_{j+1} T_{j+1} (Y touched every other step)
 
 // ---------------------------------------------------------------------------
 // storage element types: float (4 per 16 B) and bfloat16 bits (8 per 16 B)
@@ -112,31 +113,118 @@ struct StepArgs {
     void *ck_a;            // if set: T_j row-major checkpoint block (columns c0.., ld ck_ld)
     void *ck_b;            // if set: T_{j+1} checkpoint block
     int64_t ck_ld;
+    int64_t pstride;       // NP > 1: elements from one slice's panel to the next one's
 };
+
+// The rest of a row's step for one panel: T_{j+1} from the gathered sum, its
+// store and checkpoints, the Y update of caller columns c0.., partial sums.
+template <typename TS, int LPR, unsigned MODE, unsigned VAR>
+__device__ __forceinline__ void finish_row(const StepArgs &A, const TS *__restrict__ cur, const TS *__restrict__ prv,
+                                           TS *__restrict__ out, const int64_t c0, const int64_t row, const int t,
+                                           const float d, const float beta, const float aj1, const float a0,
+                                           const float (&acc)[St<TS>::VN], double &p_own, double &p_cross,
+                                           double &p_sq) {
+    constexpr bool NTH = (VAR & 1u) != 0;
+    constexpr int VN = St<TS>::VN;
+    constexpr int RS = LPR * VN;
+    typedef typename St<TS>::raw raw_t;
+    float own[VN], nxt[VN], stv[VN];
+    const raw_t own_raw = ldraw(cur + row * RS + t * VN);
+    unpack(own_raw, own);
+    if (A.ck_a) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_a) + row * A.ck_ld + c0 + t * VN) = own_raw;
+    if (MODE & M_FIRST) {
+#pragma unroll
+        for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
+    } else {
+        float pv[VN];
+        unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
+#pragma unroll
+        for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
+    }
+    const raw_t nxt_raw = st16(out + row * RS + t * VN, nxt, stv);
+    if (A.ck_b) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_b) + row * A.ck_ld + c0 + t * VN) = nxt_raw;
+    if (MODE & M_YACC) {
+        const int64_t cbase = c0 + (int64_t)t * VN;
+        float *yrow = A.Y + row * A.ldy + cbase;
+        if (cbase + VN <= A.r) {
+#pragma unroll
+            for (int q = 0; q < VN; q += 4) {
+                v4f y;
+                if (MODE & M_FIRST) {
+                    y.x = a0 * own[q] + aj1 * nxt[q];
+                    y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
+                    y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
+                    y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
+                } else if (MODE & M_YPAIR) {
+                    // a0 carries a_j here
+                    y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
+                    y.x += fmaf(a0, own[q], aj1 * nxt[q]);
+                    y.y += fmaf(a0, own[q + 1], aj1 * nxt[q + 1]);
+                    y.z += fmaf(a0, own[q + 2], aj1 * nxt[q + 2]);
+                    y.w += fmaf(a0, own[q + 3], aj1 * nxt[q + 3]);
+                } else {
+                    y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
+                    y.x = fmaf(aj1, nxt[q], y.x);
+                    y.y = fmaf(aj1, nxt[q + 1], y.y);
+                    y.z = fmaf(aj1, nxt[q + 2], y.z);
+                    y.w = fmaf(aj1, nxt[q + 3], y.w);
+                }
+                stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                if (cbase + q < A.r) {
+                    if (MODE & M_FIRST)
+                        yrow[q] = a0 * own[q] + aj1 * nxt[q];
+                    else if (MODE & M_YPAIR)
+                        yrow[q] += fmaf(a0, own[q], aj1 * nxt[q]);
+                    else
+                        yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
+                }
+            }
+        }
+    }
+    if (MODE & M_PART) {
+#pragma unroll
+        for (int q = 0; q < VN; ++q) {
+            const double o = own[q], x = stv[q];
+            if (MODE & M_FIRST) p_own += o * o;
+            p_cross += x * o;
+            p_sq += x * x;
+        }
+    }
+}
 
 // Kernel variants (VAR bits): bit 0 = non-temporal hints on the streamed
 // arrays.  The neighbour loop gathers U rows per iteration and prefetches the
 // next U column indices / weights while the gathers are in flight.
 // One row of a recurrence step (the LPR lanes of row group `t`): gather
 // sum_k w_ik T_j[k], form T_{j+1}[i] (or T_1 at the first step), store it (and
-// the checkpoints), update Y and the float64 partial sums.
-template <typename TS, int LPR, unsigned MODE, unsigned VAR>
+// the checkpoints), update Y and the float64 partial sums.  With NP > 1 one
+// launch covers NP consecutive slices (panels A.pstride elements apart,
+// caller columns c0 + q RS): the row's column indices and weights are read
+// once for all of them and every neighbour costs NP gathers.
+template <typename TS, int LPR, unsigned MODE, unsigned VAR, int NP = 1>
 __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, const int t, const float beta,
                                          const float aj1, const float a0, double &p_own, double &p_cross,
                                          double &p_sq) {
     constexpr bool NTH = (VAR & 1u) != 0;
     constexpr int VN = St<TS>::VN;
     constexpr int RS = LPR * VN;
-    constexpr int U = 8;
+    constexpr int U = NP == 1 ? 8 : 4;
     typedef typename St<TS>::raw raw_t;
     const TS *__restrict__ cur = static_cast<const TS *>(A.cur);
     const TS *__restrict__ prv = static_cast<const TS *>(A.prev);
     TS *__restrict__ out = static_cast<TS *>(A.out);
+    const int64_t ps = NP == 1 ? 0 : A.pstride;
     const bool weighted = A.w != nullptr;
     const int32_t e0 = ldx<NTH>(A.rp + row), e1 = ldx<NTH>(A.rp + row + 1);
-    float acc[VN];
+    float acc[NP][VN];
 #pragma unroll
-    for (int q = 0; q < VN; ++q) acc[q] = 0.0f;
+    for (int pn = 0; pn < NP; ++pn)
+#pragma unroll
+        for (int q = 0; q < VN; ++q) acc[pn][q] = 0.0f;
     const TS *base = cur + t * VN;
     if constexpr ((VAR & 2u) != 0) {
         // cooperative index loads: the lanes of the row group load the next U
@@ -165,9 +253,11 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
                 kc[u] = __shfl(mk[LPR < U ? u / LPR : 0], src, 64);
                 wc[u] = __shfl(mw[LPR < U ? u / LPR : 0], src, 64);
             }
-            raw_t v[U];
+            raw_t v[U][NP];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int pn = 0; pn < NP; ++pn) v[u][pn] = ldraw(base + pn * ps + (int64_t)kc[u] * RS);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int32_t ee = e + U + t + LPR * m;
@@ -179,7 +269,9 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int pn = 0; pn < NP; ++pn) fma_raw(acc[pn], wc[u], v[u][pn]);
         }
     } else {
         // padding slots gather the row itself with weight 0
@@ -202,9 +294,11 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
                 kc[u] = kn[u];
                 wc[u] = wn[u];
             }
-            raw_t v[U];
+            raw_t v[U][NP];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = ldraw(base + (int64_t)kc[u] * RS);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int pn = 0; pn < NP; ++pn) v[u][pn] = ldraw(base + pn * ps + (int64_t)kc[u] * RS);
             const int32_t en = e + U;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -216,70 +310,19 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) fma_raw(acc, wc[u], v[u]);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int pn = 0; pn < NP; ++pn) fma_raw(acc[pn], wc[u], v[u][pn]);
         }
     }
-    float own[VN], nxt[VN], stv[VN];
-    const raw_t own_raw = ldraw(cur + row * RS + t * VN);
-    unpack(own_raw, own);
-    if (A.ck_a) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_a) + row * A.ck_ld + A.c0 + t * VN) = own_raw;
     const float d = ldx<NTH>(A.diag + row);
-    if (MODE & M_FIRST) {
 #pragma unroll
-        for (int q = 0; q < VN; ++q) nxt[q] = 0.5f * fmaf(d, own[q], beta * acc[q]);
-    } else {
-        float pv[VN];
-        unpack(ldraw<NTH>(prv + row * RS + t * VN), pv);
-#pragma unroll
-        for (int q = 0; q < VN; ++q) nxt[q] = fmaf(d, own[q], fmaf(beta, acc[q], -pv[q]));
-    }
-    const raw_t nxt_raw = st16(out + row * RS + t * VN, nxt, stv);
-    if (A.ck_b) *reinterpret_cast<raw_t *>(static_cast<TS *>(A.ck_b) + row * A.ck_ld + A.c0 + t * VN) = nxt_raw;
-    if (MODE & M_YACC) {
-        const int64_t cbase = A.c0 + (int64_t)t * VN;
-        float *yrow = A.Y + row * A.ldy + cbase;
-        if (cbase + VN <= A.r) {
-#pragma unroll
-            for (int q = 0; q < VN; q += 4) {
-                v4f y;
-                if (MODE & M_FIRST) {
-                    y.x = a0 * own[q] + aj1 * nxt[q];
-                    y.y = a0 * own[q + 1] + aj1 * nxt[q + 1];
-                    y.z = a0 * own[q + 2] + aj1 * nxt[q + 2];
-                    y.w = a0 * own[q + 3] + aj1 * nxt[q + 3];
-                } else {
-                    y = ldx<NTH>(reinterpret_cast<const v4f *>(yrow + q));
-                    y.x = fmaf(aj1, nxt[q], y.x);
-                    y.y = fmaf(aj1, nxt[q + 1], y.y);
-                    y.z = fmaf(aj1, nxt[q + 2], y.z);
-                    y.w = fmaf(aj1, nxt[q + 3], y.w);
-                }
-                stx<NTH>(reinterpret_cast<v4f *>(yrow + q), y);
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < VN; ++q) {
-                if (cbase + q < A.r) {
-                    if (MODE & M_FIRST)
-                        yrow[q] = a0 * own[q] + aj1 * nxt[q];
-                    else
-                        yrow[q] = fmaf(aj1, nxt[q], yrow[q]);
-                }
-            }
-        }
-    }
-    if (MODE & M_PART) {
-#pragma unroll
-        for (int q = 0; q < VN; ++q) {
-            const double o = own[q], x = stv[q];
-            if (MODE & M_FIRST) p_own += o * o;
-            p_cross += x * o;
-            p_sq += x * x;
-        }
-    }
+    for (int pn = 0; pn < NP; ++pn)
+        finish_row<TS, LPR, MODE, VAR>(A, cur + pn * ps, prv + pn * ps, out + pn * ps, A.c0 + (int64_t)pn * RS, row,
+                                       t, d, beta, aj1, a0, acc[pn], p_own, p_cross, p_sq);
 }
 
-template <typename TS, int LPR, unsigned MODE, unsigned VAR>
+template <typename TS, int LPR, unsigned MODE, unsigned VAR, int NP = 1>
 __global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
     constexpr int RPW = 64 / LPR;
     constexpr int ROWS = RPW * (NT / 64);
@@ -289,7 +332,9 @@ __global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
     const int sub = lane / LPR;
     const float beta = A.beta[0];
     const float aj1 = (MODE & M_YACC) ? (float)A.coeffs[A.j + 1] : 0.0f;
-    const float a0 = ((MODE & M_YACC) && (MODE & M_FIRST)) ? (float)A.coeffs[0] : 0.0f;
+    const float a0 = !(MODE & M_YACC) ? 0.0f
+                     : (MODE & M_FIRST) ? (float)A.coeffs[0]
+                     : (MODE & M_YPAIR) ? (float)A.coeffs[A.j] : 0.0f;
     double p_own = 0.0, p_cross = 0.0, p_sq = 0.0;
     const int64_t ntiles = (A.n + ROWS - 1) / ROWS;
     if ((VAR & 4u) != 0 && gridDim.x >= 8) {
@@ -304,13 +349,13 @@ __global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
         for (int64_t tile = t0 + loc; tile < t1; tile += nx) {
             const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
             if (row >= A.n) continue;
-            step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
+            step_row<TS, LPR, MODE, VAR, NP>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
         }
     } else {
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
             if (row >= A.n) continue;
-            step_row<TS, LPR, MODE, VAR>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
+            step_row<TS, LPR, MODE, VAR, NP>(A, row, t, beta, aj1, a0, p_own, p_cross, p_sq);
         }
     }
     if (MODE & M_PART) {
@@ -432,6 +477,7 @@ struct Plan {
     int rs;      // panel width in elements = lpr * VN
     int nslices;
     unsigned var;
+    int np;      // slices per launch: 1, or all of them (variant bit 3)
 };
 
 int vn_of(asc_dtype dt) { return dt == ASC_F32 ? 4 : 8; }
@@ -454,6 +500,10 @@ bool valid_rs(int rs, asc_dtype dt) {
     return rs == 2 * vn || rs == 4 * vn || rs == 8 * vn || rs == 16 * vn;
 }
 
+// Variant bit 3 puts every slice in one launch (np = nslices) where the
+// multi-panel kernel exists: 8 lanes per row and 2 to 4 slices.
+bool multi_panel(int lpr, int nslices) { return lpr == 8 && nslices >= 2 && nslices <= 4; }
+
 Plan plan_for(int rs, unsigned var, int64_t r, asc_dtype dt) {
     Plan P;
     const int vn = vn_of(dt);
@@ -461,6 +511,7 @@ Plan plan_for(int rs, unsigned var, int64_t r, asc_dtype dt) {
     P.lpr = rs / vn;
     P.nslices = (int)((r + rs - 1) / rs);
     P.var = var;
+    P.np = ((var & 8u) != 0 && multi_panel(P.lpr, P.nslices)) ? P.nslices : 1;
     return P;
 }
 
@@ -487,17 +538,19 @@ int grid_for(int64_t n, int lpr) {
     return (int)b;
 }
 
-template <typename TS, int LPR, unsigned VAR>
+template <typename TS, int LPR, unsigned VAR, int NP = 1>
 hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
     switch (mode) {
-        case 0: cheb_step<TS, LPR, 0, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 1: cheb_step<TS, LPR, 1, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 2: cheb_step<TS, LPR, 2, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 3: cheb_step<TS, LPR, 3, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 4: cheb_step<TS, LPR, 4, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 5: cheb_step<TS, LPR, 5, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 6: cheb_step<TS, LPR, 6, VAR><<<grid, NT, 0, s>>>(A); break;
-        case 7: cheb_step<TS, LPR, 7, VAR><<<grid, NT, 0, s>>>(A); break;
+        case 0: cheb_step<TS, LPR, 0, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 1: cheb_step<TS, LPR, 1, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 2: cheb_step<TS, LPR, 2, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 3: cheb_step<TS, LPR, 3, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 4: cheb_step<TS, LPR, 4, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 5: cheb_step<TS, LPR, 5, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 6: cheb_step<TS, LPR, 6, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 7: cheb_step<TS, LPR, 7, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 10: cheb_step<TS, LPR, 10, VAR, NP><<<grid, NT, 0, s>>>(A); break;
+        case 14: cheb_step<TS, LPR, 14, VAR, NP><<<grid, NT, 0, s>>>(A); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -537,6 +590,15 @@ hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const
     return hipErrorInvalidValue;
 }
 
+// Y accumulation of recurrence step j >= 1 of an order-p filter (step j
+// forms T_{j+1}): even steps add the pair a_j T_j + a_{j+1} T_{j+1}, odd steps
+// leave Y alone, except the last step, which adds its own a_p T_p; step 0
+// writes a_0 T_0 + a_1 T_1.  Every term is added exactly once.
+unsigned y_mode(int j, int p) {
+    if (j % 2 == 0) return M_YACC | M_YPAIR;
+    return j == p - 1 ? M_YACC : 0u;
+}
+
 size_t esize(asc_dtype dt) { return dt == ASC_F32 ? 4 : 2; }
 
 // checkpoint blocks: (T_{sc}, T_{sc+1}) for segment starts sc = 0, c, 2c, ... < p,
@@ -573,15 +635,20 @@ size_t filter_ws_layout(int64_t n, int rs_max, int nslices, asc_dtype dt, int st
     f.part = a.take<double>((size_t)steps_part * kMaxGrid * 3);
     f.sums = a.take<double>((size_t)nslices * steps_sum * 3);
     f.first = a.take<double>(64);
-    f.panelA = a.take<char>((size_t)n * rs_max * esize(dt));
-    f.panelB = a.take<char>((size_t)n * rs_max * esize(dt));
+    // room for up to 4 slice panels, each rounded up to 256 bytes
+    f.panelA = a.take<char>((size_t)n * rs_max * esize(dt) + 4 * 256);
+    f.panelB = a.take<char>((size_t)n * rs_max * esize(dt) + 4 * 256);
     if (out) *out = f;
     return a.size();
 }
 
 int rs_for_ws(int64_t r, asc_dtype dt) {
-    // the workspace must hold the widest panel any plan may pick
-    return std::max(default_rs(r, dt), dt == ASC_F32 ? 64 : 128);
+    // the workspace must hold the widest panel any plan may pick, and the
+    // panels of every slice when one launch covers them all
+    const int w8 = 8 * vn_of(dt);
+    const int64_t ns8 = (r + w8 - 1) / w8;
+    const int all = multi_panel(8, (int)std::min<int64_t>(ns8, 5)) ? (int)(ns8 * w8) : 0;
+    return std::max(std::max(default_rs(r, dt), dt == ASC_F32 ? 64 : 128), all);
 }
 
 asc_status check_common(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig, int64_t r,
