@@ -41,11 +41,12 @@ HBM_PEAK_GBS = 8000.0
 # variant; valid only while the kernel source is the one measured (sha1 of the
 # step-kernel region of recurrence.hpp), otherwise reported null.
 STEP_TRAFFIC = {
-    "src_sha1": "a95ff79e15b5097e0c749979a820bc8e22aa4025",
+    "src_sha1": "7770077e6e0e8b5618d05ee3d3db1d4c8837c990",
     "workload": "sbm_n1e6_k50dir_d30_r96_p150",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    # (slice_cols, variant) -> (FETCH_SIZE, WRITE_SIZE), average over 2664 dispatches
-    "kib_per_launch": {(32, 0): (2233034.81, 250000.0), (32, 4): (2223176.33, 250000.0)},
+    # (slice_cols, variant) -> (FETCH_SIZE, WRITE_SIZE) in KiB, average over the
+    # 2700 step launches of 6 filters (steps that update Y and steps that do not)
+    "kib_per_launch": {(32, 4): (2192482.04, 188338.45)},
 }
 
 
