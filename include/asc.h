@@ -399,8 +399,9 @@ asc_status asc_ari_pairs(const int32_t *labels, int64_t n, int64_t ldl, int J, i
  *               weights once (it gathers all slices' panels at once, so it
  *               pays where they fit the Infinity Cache together); with bit 3
  *               only bit 2 of the others applies.  0 <= variant <= 15.
- * Every filter step writes T_{j+1}; Y is read and updated on every other step
- * (a_j T_j + a_{j+1} T_{j+1} together) and on the last one.
+ * Every filter step writes T_{j+1}; with float32 states Y is read and updated
+ * on every other step (a_j T_j + a_{j+1} T_{j+1} together) and on the last
+ * one; with bfloat16 states on every step, from T_{j+1} before its rounding.
  * asc_autotune_filter times every candidate on the caller's graph and signals
  * for probe_steps recurrence steps (Y and ws are scratch; needs ws of
  * asc_filter_workspace(n, r, sig, 1) bytes), records the fastest and returns

@@ -337,7 +337,7 @@ asc_status enqueue_batch(BatchPlan &b, const double *lmax, const void *R, int64_
             B.S.prev = j == 0 ? nullptr : prev;
             B.S.out = prev;
             B.S.j = j;
-            hipError_t e = launch_batch(b.sig, b.P.lpr, j == 0 ? (M_FIRST | M_YACC) : y_mode(j, b.p), B, b.grid, s);
+            hipError_t e = launch_batch(b.sig, b.P.lpr, j == 0 ? (M_FIRST | M_YACC) : y_mode(j, b.p, b.sig), B, b.grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "batch_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
         }

@@ -172,7 +172,7 @@ asc_status run_filter(const asc_graph *g, const double *lmax, const double *coef
             const bool ck = ckb && (j % ckpt_stride == 0);
             A.ck_a = ck ? ck_block(j / ckpt_stride, 0) : nullptr;
             A.ck_b = ck ? ck_block(j / ckpt_stride, 1) : nullptr;
-            e = launch_plan(P, sig, y_mode(j, p) | (last ? M_PART : 0u), A, grid, s);
+            e = launch_plan(P, sig, y_mode(j, p, sig) | (last ? M_PART : 0u), A, grid, s);
             if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
             std::swap(cur, prev);
         }
@@ -543,8 +543,8 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
             A.j = 0;
             void *cur = F.panelA, *prev = F.panelB;
             float ms = 0.f;
-            // steps in pairs, as the filter runs them: one that adds a pair of
-            // terms to Y, one that leaves Y alone
+            // steps in pairs, as the filter runs them (float32: one that adds a
+            // pair of terms to Y, one that leaves Y alone; bfloat16: Y on both)
             for (int it = -1; it < probe_steps && st == ASC_OK; ++it) {
                 if (it == 0) (void)hipEventRecord(e0, s);
                 for (int half = 0; half < 2 && st == ASC_OK; ++half) {
@@ -553,7 +553,8 @@ asc_status autotune_filter(const asc_graph *g, const double *lmax, const void *R
                         A.cur = cur;
                         A.prev = prev;
                         A.out = prev;
-                        hipError_t e = launch_plan(P, sig, half == 0 ? (M_YACC | M_YPAIR) : 0u, A, grid, s);
+                        const unsigned ym = sig == ASC_F32 ? (half == 0 ? (M_YACC | M_YPAIR) : 0u) : M_YACC;
+                        hipError_t e = launch_plan(P, sig, ym, A, grid, s);
                         if (e != hipSuccess) {
                             st = fail(ASC_ERR_HIP, "autotune launch failed: %s", hipGetErrorString(e));
                             break;

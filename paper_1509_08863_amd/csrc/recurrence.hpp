@@ -591,10 +591,13 @@ hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const
 }
 
 // Y accumulation of recurrence step j >= 1 of an order-p filter (step j
-// forms T_{j+1}): even steps add the pair a_j T_j + a_{j+1} T_{j+1}, odd steps
-// leave Y alone, except the last step, which adds its own a_p T_p; step 0
-// writes a_0 T_0 + a_1 T_1.  Every term is added exactly once.
-unsigned y_mode(int j, int p) {
+// forms T_{j+1}): with float32 states, even steps add the pair
+// a_j T_j + a_{j+1} T_{j+1}, odd steps leave Y alone, except the last step,
+// which adds its own a_p T_p; step 0 writes a_0 T_0 + a_1 T_1.  Every term is
+// added exactly once.  With bfloat16 states every step adds its T_{j+1} as
+// computed, before rounding to storage (T_j as read back would be rounded).
+unsigned y_mode(int j, int p, asc_dtype dt) {
+    if (dt != ASC_F32) return M_YACC;
     if (j % 2 == 0) return M_YACC | M_YPAIR;
     return j == p - 1 ? M_YACC : 0u;
 }
