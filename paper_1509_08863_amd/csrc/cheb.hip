@@ -14,7 +14,9 @@
 // One recurrence step (kernel cheb_step):
 //   T_{j+1}[i] = d_i T_j[i] + beta sum_k w_ik T_j[k] - T_{j-1}[i],
 //   d_i = 4 s_i / lmax - 2, beta = -4 / lmax   (= 2 Lt T_j - T_{j-1}),
-//   Y[i] += a_{j+1} T_{j+1}[i]                  (fused, float32),
+//   Y[i] += a_j T_j[i] + a_{j+1} T_{j+1}[i]      (fused, float32, every other
+//                                                step; bfloat16 states: Y[i] +=
+//                                                a_{j+1} T_{j+1}[i] every step),
 // with LPR lanes of a wavefront per row (64/LPR rows per wavefront), each
 // lane owning 16 bytes of the row: the gather of T_j[k] is one coalesced
 // 16*LPR-byte segment per neighbour.  Optional float64 partial sums per block
