@@ -177,3 +177,12 @@ def test_batch_plan_and_tuner_workspace_are_host_only():
         assert L.asc_batch_workspace(h) == ws  # rejected calls leave the plan alone
     finally:
         assert L.asc_batch_destroy(h) == _abi.ASC_OK
+
+
+def test_gather_probe_rejects_before_launch():
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.asc_gather_probe(None, 10, fake, 5, fake, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_gather_probe(fake, 0, fake, 5, fake, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_gather_probe(ctypes.c_void_p(0x1004), 10, fake, 5, fake, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_gather_probe(fake, 10, fake, 0, fake, None) == _abi.ASC_OK  # nothing to read, no launch

@@ -64,3 +64,15 @@ def test_single_signal_column_and_zero_weight_edges():
     a = oracle.cheb_coeffs(0.2 * lmax, lmax, 40)
     Y = host(asc.cheb_filter(G, scalar(lmax), to_dev(a), block_f32(Rs)))
     assert rel_fro(Y, oracle.cheb_filter(L, lmax, a, R64)) <= 1e-5
+
+
+def test_gather_probe_runs_on_a_graph_pattern():
+    # the measurement aid behind the bench's gather floor: reads rows of a
+    # zero table at the graph's column indices; the sentinel is never met
+    import torch
+    g = W.random_weighted(3000, 0.01, 4)
+    table = torch.zeros(g.n, 32, dtype=torch.float32, device="cuda")
+    sink = torch.full((1,), -1.0, dtype=torch.float32, device="cuda")
+    ci = to_dev(g.col_idx.astype(np.int32))
+    asc.gather_probe(table, ci, sink)
+    assert host(sink)[0] == -1.0
