@@ -143,6 +143,88 @@ __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F,
     }
 }
 
+// k > 32 with centroids that fit LDS as float64: one lane per centroid (64
+// per group) and RB rows per wavefront pass, the centroids staged transposed
+// as float64 (Cd[col][kp]), so one LDS read and no conversion serve RB rows.
+// Per (row, centroid) the arithmetic and the lowest-index argmin are those of
+// assign_kernel (identical labels).
+template <int RB>
+__global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                         int64_t ldf, const float *__restrict__ Cg, int k,
+                                                         int32_t *__restrict__ labels, float *__restrict__ dist2,
+                                                         double *__restrict__ dist64, Bat bt) {
+#pragma clang fp contract(off)
+    extern __shared__ double Cd[];
+    F += fblk(bt);
+    Cg += blockIdx.y * bt.c;
+    labels += blockIdx.y * bt.l;
+    if (dist2) dist2 += blockIdx.y * bt.l;
+    if (dist64) dist64 += blockIdx.y * bt.l;
+    const int kp = (k + 63) & ~63;
+    for (int64_t q = threadIdx.x; q < (int64_t)kp * r; q += NT) {
+        const int64_t col = q / kp;
+        const int c = (int)(q - col * kp);
+        Cd[q] = c < k ? (double)Cg[(int64_t)c * r + col] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
+    for (int64_t i = wave0 * RB; i < n; i += nwaves * RB) {
+        const int64_t i0 = __builtin_amdgcn_readfirstlane((int)i);
+        const float *f[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) f[q] = F + (i0 + q < n ? i0 + q : n - 1) * ldf;
+        double best[RB];
+        int bc[RB];
+        for (int g = 0; g < kp; g += 64) {
+            const int c = g + lane;
+            double d[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) d[q] = 0.0;
+            for (int64_t col = 0; col < r; ++col) {
+                const double cv = Cd[col * kp + c];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const double diff = (double)f[q][col] - cv;
+                    const double sq = diff * diff;
+                    d[q] = d[q] + sq;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                double dq = d[q];
+                int ci = c;
+                if (c >= k) {
+                    dq = __builtin_huge_val();
+                    ci = 0x7fffffff;
+                }
+                for (int off = 1; off < 64; off <<= 1) {
+                    const double d2 = __shfl_xor(dq, off, 64);
+                    const int c2 = __shfl_xor(ci, off, 64);
+                    better(dq, ci, d2, c2);
+                }
+                if (g == 0) {
+                    best[q] = dq;
+                    bc[q] = ci;
+                } else {
+                    better(best[q], bc[q], dq, ci);
+                }
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (i0 + q < n) {
+                    labels[i0 + q] = bc[q];
+                    if (dist2) dist2[i0 + q] = (float)best[q];
+                    if (dist64) dist64[i0 + q] = best[q];
+                }
+            }
+        }
+    }
+}
+
 // k <= 32: 64/KP rows per wavefront and KP lanes (one per centroid) per row,
 // so small k keeps the lanes busy; the centroids are staged transposed in LDS
 // as float64 (Cd[col][KP]).  The arithmetic per (row, centroid) and the
@@ -408,6 +490,15 @@ void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C
             case 16: assign_grouped<16>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
             default: assign_grouped<32>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
         }
+    }
+    const int64_t cap0 = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
+    const size_t dbytes = (size_t)((k + 63) & ~63) * r * sizeof(double);
+    if (dbytes <= 64 * 1024) {
+        constexpr int RB = 4;
+        const int64_t want = (n + (NT / 64) * RB - 1) / ((NT / 64) * RB);
+        const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap0)), (unsigned)b.count);
+        assign_rows_kernel<RB><<<grid, NT, dbytes, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
+        return;
     }
     const size_t cbytes = (size_t)((k + 63) & ~63) * r * sizeof(float);
     const int use_lds = cbytes <= 64 * 1024;

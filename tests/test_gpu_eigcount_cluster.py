@@ -98,7 +98,8 @@ def test_normalize_matches_oracle():
 
 
 @pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (1000, 96, 50), (333, 7, 3), (64, 130, 200), (1000, 130, 7),
-                                   (777, 5, 2), (2000, 40, 32), (2000, 40, 33), (1500, 256, 32), (301, 3, 1)])
+                                   (777, 5, 2), (2000, 40, 32), (2000, 40, 33), (1500, 256, 32), (301, 3, 1),
+                                   (1001, 32, 100), (3, 40, 40), (70, 64, 64), (513, 100, 80)])
 def test_kmeans_assign_bit_exact(n, r, k):
     rng = np.random.default_rng(n + k)
     F = rng.standard_normal((n, r)).astype(np.float32)
