@@ -461,6 +461,27 @@ def order_for(lambda_c: float, lmax: float, delta: float = 0.1, band_rel: float 
     return int(ms.cpu()[0, 0])
 
 
+def lambda_k_filter_auto(g: Graph, lmax: torch.Tensor, k: int, R: torch.Tensor, delta: float = 0.1,
+                         band_rel: float = 0.5, p_count: int = 150, steps: int = 12, m_max: int = 4000,
+                         grid: int = 2049, Y: torch.Tensor | None = None):
+    """Steps 2-5 of Sec. 4.1 with the polynomial order taken from the order
+    table (note on m, Sec. 2.4): lambda_k by the dichotomy on Chebyshev moments
+    of order p_count, then p = m*(lambda_k / lmax; delta) with a transition
+    band of band_rel * lambda_k, then the order-p filter at lambda_k.  Reads
+    lambda_k, lmax and m* back to the host (the order sizes the recurrence).
+    Returns (Y, lambda_k, traj, p); raises ValueError if no order up to m_max
+    meets delta."""
+    lam, traj = eigcount_lambda_k(g, lmax, k, p_count, steps, R)
+    lam_h, lmax_h = float(lam.cpu()[0]), float(lmax.reshape(-1)[0].cpu())
+    if not 0.0 < lam_h < lmax_h:
+        raise ValueError(f"lambda_k = {lam_h} outside (0, lambda_max = {lmax_h}): no low-pass order to choose")
+    p = order_for(lam_h, lmax_h, delta, band_rel, m_max, grid, device=R.device)
+    if p > m_max:
+        raise ValueError(f"no order up to {m_max} meets delta = {delta} outside the band")
+    Y = cheb_filter(g, lmax, cheb_coeffs(lam, lmax, p), R, Y)
+    return Y, lam, traj, p
+
+
 def ari_pairs(labels: torch.Tensor, k: int):
     """Adjusted Rand index of every pair (a, b), a < b, of the J labellings in
     the rows of labels (int32 J x n, values in [0, k)); returns (ari, mean)."""

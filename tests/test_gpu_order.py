@@ -4,10 +4,12 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from oracle import order
+import workloads as W
 import paper_1509_08863_amd as asc
 
-from gpu_util import DEV, host
+from gpu_util import DEV, host, upload_graph, block_f32, scalar, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -41,3 +43,28 @@ def test_order_for_relative_band():
     rho = lc / lmax
     assert m == order.m_star(rho, 0.1, 1000, 0.5 * rho, 2049)
     assert 100 < m < 1000
+
+
+def test_lambda_k_filter_with_the_order_from_the_table():
+    # the table feeds p (note on m, Sec. 2.4): lambda_k from the moment
+    # dichotomy, p = m*(lambda_k / lmax; delta) with a band of half the cut-off,
+    # then the order-p filter; checked against the oracle's m* and filter
+    g = W.config_graph(1)
+    G = upload_graph(g)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+    lmax = oracle.lmax_estimate(L, oracle.strength(g.n, g.row_ptr, g.col_idx, None), W.start_vector(g.n, 1), 60)
+    Rs, R64 = W.signals(g.n, 16, 4)
+    k, p_count, steps = 10, 50, 12
+    Y, lam, traj, p = asc.lambda_k_filter_auto(G, scalar(lmax), k, block_f32(Rs), delta=0.1, band_rel=0.5,
+                                               p_count=p_count, steps=steps, m_max=2000)
+    lam_h = float(host(lam)[0])
+    rho = lam_h / lmax
+    assert p == order.m_star(rho, 0.1, 2000, 0.5 * rho, 2049)
+    print("lambda_k / lmax", rho, "order", p)
+    a = oracle.cheb_coeffs(lam_h, lmax, p)
+    assert rel_fro(host(Y), oracle.cheb_filter(L, lmax, a, R64)) <= 1e-5
+    est, traj_ref = oracle.dichotomy_moments(L, lmax, k, p_count, steps, R64)
+    if np.all(np.abs(traj_ref[:, 1] - (k - 0.5)) > 1e-3):
+        assert lam_h == est
+    with pytest.raises(ValueError):
+        asc.lambda_k_filter_auto(G, scalar(lmax), k, block_f32(Rs), delta=1e-9, p_count=p_count, m_max=40)
