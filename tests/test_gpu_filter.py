@@ -241,3 +241,24 @@ def test_tune_table_roundtrip(tmp_path):
     asc.tune_load(path)
     assert asc.tune_get(G, 32, torch.float32) == (16, 1)
     asc.tune_set(G, 32, torch.float32, 0, 0)
+
+
+@pytest.mark.parametrize("n,blocks,weighted", [(300_000, 2, True), (700_000, 3, False)])
+def test_lmax_column_blocked_products_match_oracle(n, blocks, weighted):
+    # above 2 MB of float64 vector the Lanczos product runs as passes over
+    # column ranges (each range L2-resident); the result is the oracle's
+    g = W.sbm(W.equal_sizes(n, 4), 8.0, 0.2, 31 + n)
+    assert (8 * n + (2 << 20) - 1) // (2 << 20) == blocks
+    w = None
+    if weighted:  # symmetric weights: a function of the unordered pair
+        rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+        cols = g.col_idx.astype(np.int64)
+        w = (0.5 + ((rows * cols) % 7) / 7.0).astype(np.float32)
+    G = upload_graph(g, w=w) if weighted else upload_graph(g, unit_as_null=True)
+    w64 = None if w is None else w.astype(np.float64)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w64)
+    s = oracle.strength(g.n, g.row_ptr, g.col_idx, w64)
+    v0 = W.start_vector(g.n, 6)
+    ref = oracle.lmax_estimate(L, s, v0, 30)
+    _, got = asc.lmax_estimate(G, to_dev(v0), 30, host=True)
+    assert got == pytest.approx(ref, rel=1e-9)
