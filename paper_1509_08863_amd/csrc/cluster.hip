@@ -225,6 +225,177 @@ __global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict
     }
 }
 
+// k-means assignment on the matrix cores (2 <= k <= 16 NTILE; the centroids
+// and each wavefront's 16 rows are staged in LDS).  A wavefront takes 16
+// rows: v_mfma_f32_16x16x4f32 forms the dot products with the centroids as
+// the A operand and the rows as the B operand, so lane l holds row l % 16 and
+// centroids 16 T + 4 (l / 16) + v (v = 0..3) of tile T; the approximate
+// distance is d~ = (|f|^2 + |c|^2) - 2 f.c with the norms in float64.  With
+//   E(c) = 3 (r + 2) 2^-24 |f| |c| + 1e-12 (|f|^2 + |c|^2)
+// (1.5 times the standard bound 2 gamma_r |f| |c| on the float32 dot
+// product's contribution, plus the float64 definition's own rounding), the
+// exact distance of c lies in [d~(c) - E(c), d~(c) + E(c)].  Let b be the
+// float32 winner; every centroid whose interval reaches below d~(b) + E(b)
+// (b itself, and any near tie) gets its float64 distance by the definition
+// (squared differences summed column by column, no fused multiply-add) from
+// the lane that holds it, and the least (distance, index) among them is the
+// row's result: the others cannot be nearer.  Labels and distances therefore
+// equal the definition's.  A row with non-finite values evaluates every
+// centroid.
+template <int NTILE>
+__global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                         int64_t ldf, const float *__restrict__ Cg, int k,
+                                                         int32_t *__restrict__ labels, float *__restrict__ dist2,
+                                                         double *__restrict__ dist64, Bat bt) {
+#pragma clang fp contract(off)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int KC = 16 * NTILE;
+    extern __shared__ double lds_d[];
+    const int RP = (int)((r + 3) & ~int64_t(3)) + 1;      // odd stride: fewer bank conflicts
+    double *cn = lds_d;                                   // |c|^2, KC values
+    double *cs = lds_d + KC;                              // |c|, KC values
+    float *Cs = reinterpret_cast<float *>(lds_d + 2 * KC);  // [KC][RP], zero-padded
+    float *Fs = Cs + KC * RP + (threadIdx.x >> 6) * 16 * RP;  // this wavefront's 16 rows
+    F += fblk(bt);
+    Cg += blockIdx.y * bt.c;
+    labels += blockIdx.y * bt.l;
+    if (dist2) dist2 += blockIdx.y * bt.l;
+    if (dist64) dist64 += blockIdx.y * bt.l;
+    for (int q = threadIdx.x; q < KC * RP; q += NT) {
+        const int c = q / RP, col = q - c * RP;
+        Cs[q] = (c < k && col < r) ? Cg[(int64_t)c * r + col] : 0.0f;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < KC; c += NT) {
+        double a = 0.0;
+        for (int col = 0; col < r; ++col) {
+            const double x = Cs[c * RP + col];
+            a += x * x;
+        }
+        cn[c] = a;
+        cs[c] = sqrt(a);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int steps = (int)((r + 3) >> 2);
+    const double ecoef = 3.0 * (double)(r + 2) * 0x1p-24;
+    const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
+    for (int64_t g = wave0; g * 16 < n; g += nwaves) {
+        const int64_t row = g * 16 + li;
+        const bool live = row < n;
+        // the wavefront's 16 rows into its own LDS rows, with coalesced loads
+        // (zeros past n and past r)
+        for (int q = lane; q < 16 * RP; q += 64) {
+            const int rl = q / RP, col = q - rl * RP;
+            const int64_t rr = g * 16 + rl;
+            Fs[q] = (rr < n && col < r) ? F[rr * ldf + col] : 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const float *fr = Fs + li * RP;
+        v4f acc[NTILE];
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        double nf = 0.0;
+#pragma unroll 4
+        for (int st = 0; st < steps; ++st) {
+            const int col = 4 * st + lk;
+            const float b = fr[col];
+            nf += (double)b * (double)b;
+#pragma unroll
+            for (int t = 0; t < NTILE; ++t) {
+                const float a = Cs[(16 * t + li) * RP + col];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        // |f|^2 of row li: the four lanes li, li+16, li+32, li+48 hold its columns
+        nf += __shfl_xor(nf, 16, 64);
+        nf += __shfl_xor(nf, 32, 64);
+        const double sf = sqrt(nf);
+        // the float32 winner of the row and its upper bound d~ + E
+        double bd = __builtin_huge_val(), bub = __builtin_huge_val();
+        int bc = 0x7fffffff;
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * t + 4 * lk + v;
+                if (c < k) {
+                    const double dd = (cn[c] + nf) - 2.0 * (double)acc[t][v];
+                    if (dd < bd || (dd == bd && c < bc)) {
+                        bd = dd;
+                        bc = c;
+                        bub = dd + (ecoef * sf * cs[c] + 1e-12 * (nf + cn[c]));
+                    }
+                }
+            }
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+            const double obd = __shfl_xor(bd, off, 64), obub = __shfl_xor(bub, off, 64);
+            const int obc = __shfl_xor(bc, off, 64);
+            if (obd < bd || (obd == bd && obc < bc)) {
+                bd = obd;
+                bc = obc;
+                bub = obub;
+            }
+        }
+        // every centroid that could be nearest, by the float64 definition
+        const bool all = !(bub < __builtin_huge_val());  // non-finite row: every centroid
+        uint32_t need = 0;  // bit 4 t + v: centroid 16 t + 4 lk + v needs its float64 distance
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * t + 4 * lk + v;
+                if (c >= k) continue;
+                const double dd = (cn[c] + nf) - 2.0 * (double)acc[t][v];
+                const double lb = dd - (ecoef * sf * cs[c] + 1e-12 * (nf + cn[c]));
+                if (all || lb <= bub) need |= 1u << (4 * t + v);
+            }
+        if (!live) need = 0;
+        // one pass of the column loop per needed centroid of the busiest lane
+        // (usually one: the winner's own lane)
+        double ed = __builtin_huge_val();
+        int ec = 0x7fffffff;
+        while (__ballot(need != 0)) {
+            const int slot = need ? __builtin_ctz(need) : -1;
+            need &= need - 1;
+            if (slot >= 0) {
+                const int c = 16 * (slot >> 2) + 4 * lk + (slot & 3);
+                const float *cr = Cs + c * RP;
+                double d = 0.0;
+                for (int64_t col = 0; col < r; ++col) {
+                    const double diff = (double)fr[col] - (double)cr[col];
+                    const double sq = diff * diff;
+                    d = d + sq;
+                }
+                if (ec == 0x7fffffff) {  // the first is taken as is (also when d is NaN)
+                    ed = d;
+                    ec = c;
+                } else {
+                    better(ed, ec, d, c);
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+            const double od = __shfl_xor(ed, off, 64);
+            const int oc = __shfl_xor(ec, off, 64);
+            if (oc != 0x7fffffff && (ec == 0x7fffffff || od < ed || (od == ed && oc < ec))) {
+                ed = od;
+                ec = oc;
+            }
+        }
+        if (live && lk == 0) {
+            labels[row] = ec;
+            if (dist2) dist2[row] = (float)ed;
+            if (dist64) dist64[row] = ed;
+        }
+        __builtin_amdgcn_wave_barrier();  // every lane is done with Fs before the next rows
+    }
+}
+
 // k <= 32: 64/KP rows per wavefront and KP lanes (one per centroid) per row,
 // so small k keeps the lanes busy; the centroids are staged transposed in LDS
 // as float64 (Cd[col][KP]).  The arithmetic per (row, centroid) and the
@@ -478,8 +649,31 @@ void assign_grouped(const float *F, int64_t n, int64_t r, int64_t ldf, const flo
                                                                                dist64, to_bat(b));
 }
 
+template <int NTILE>
+void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
+                 float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
+    constexpr int KC = 16 * NTILE;
+    const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
+    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NT / 64) * 16) * rp * sizeof(float);
+    const int64_t want = (n + (NT / 64) * 16 - 1) / ((NT / 64) * 16);
+    const int64_t cap = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
+    assign_mfma_kernel<NTILE><<<grid, NT, lds, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
+}
+
 void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
+    // matrix cores while the centroids and 4 x 16 staged rows fit 64 KB of LDS
+    const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
+    const int kc = ((k + 15) / 16) * 16;
+    if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + 64) * rpad * 4 <= 64 * 1024) {
+        switch ((k + 15) / 16) {
+            case 1: assign_mfma<1>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            case 2: assign_mfma<2>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            case 3: assign_mfma<3>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+            default: assign_mfma<4>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
+        }
+    }
     int kp2 = 2;
     while (kp2 < k) kp2 *= 2;
     if (kp2 <= 32 && (size_t)kp2 * r * sizeof(double) <= 64 * 1024) {

@@ -157,3 +157,24 @@ def test_one_pass_lambda_k_filter(r, p):
     if np.all(np.abs(traj_ref[:, 1] - (k - 0.5)) > 1e-3):
         Yref = oracle.cheb_filter(L, lmax, oracle.cheb_coeffs(est_ref, lmax, p), R64)
         assert rel_fro(host(Y), Yref) <= 1e-5
+
+
+@pytest.mark.parametrize("n,r,k", [(4000, 96, 50), (3000, 24, 10), (2500, 128, 64), (1000, 4, 2)])
+def test_kmeans_assign_near_ties_stay_exact(n, r, k):
+    # rows at midpoints of centroid pairs (plus noise far below the float32
+    # error of the dot-product form), exact midpoints, duplicated centroids
+    # and a non-finite row: the matrix-core proposals cannot certify these,
+    # the float64 rerun decides, and the labels equal the definition's
+    rng = np.random.default_rng(r + k)
+    C = rng.standard_normal((k, r)).astype(np.float32)
+    C[k - 1] = C[0]
+    a = rng.integers(0, k, n)
+    b = rng.integers(0, k, n)
+    F = (0.5 * (C[a].astype(np.float64) + C[b].astype(np.float64))).astype(np.float32)
+    F[: n // 2] += (rng.standard_normal((n // 2, r)) * 1e-6).astype(np.float32)
+    F[n // 3] = np.nan
+    labels, dist2 = asc.kmeans_assign(block_f32(F), to_dev(C))
+    ok = np.all(np.isfinite(F), axis=1)
+    lab_ref, d_ref = oracle.kmeans_assign(F[ok], C)
+    np.testing.assert_array_equal(host(labels)[ok], lab_ref)
+    np.testing.assert_array_equal(host(dist2)[ok], d_ref.astype(np.float32))
