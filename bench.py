@@ -46,7 +46,7 @@ STEP_TRAFFIC = {
     "fetch_scale": 2.0, "write_scale": 1.0,
     # (slice_cols, variant) -> (FETCH_SIZE, WRITE_SIZE) in KiB, average over the
     # 2700 step launches of 6 filters (steps that update Y and steps that do not)
-    "kib_per_launch": {(32, 4): (2192482.04, 188338.45)},
+    "kib_per_launch": {(32, 4): (2192482.04, 188338.45), (32, 0): (2202944.85, 188338.45)},
 }
 
 
