@@ -549,6 +549,67 @@ __global__ __launch_bounds__(256) void update_partial4_kernel(const float *__res
             (int64_t)S4[3 * stride + kr + q];
 }
 
+// r <= 32: the 64 lanes of a wavefront form 64 / rs slots of rs lanes (rs the
+// power of two >= r, one lane per column); each of the block's 4 (64 / rs)
+// slots sums its own contiguous share of the block's rows, in order, into
+// its own LDS copy, and the copies are added in slot order (deterministic)
+__global__ __launch_bounds__(256) void update_slots_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                           int64_t ldf, const int32_t *__restrict__ labels, int k,
+                                                           int64_t rows_per_block, double *__restrict__ part,
+                                                           int64_t *__restrict__ pcount, Bat bt, int rs) {
+    extern __shared__ double SS[];  // (4 * 64 / rs) x (k*r sums, k counts)
+    const int SL = 64 / rs;
+    const int ncopy = 4 * SL;
+    const int64_t kr = (int64_t)k * r;
+    const int64_t stride = kr + k;
+    F += fblk(bt);
+    labels += blockIdx.y * bt.l;
+    part += (int64_t)blockIdx.y * gridDim.x * kr;
+    pcount += (int64_t)blockIdx.y * gridDim.x * k;
+    for (int64_t q = threadIdx.x; q < ncopy * stride; q += blockDim.x) SS[q] = 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / rs, col = lane & (rs - 1);
+    const int id = wave * SL + slot;
+    double *S = SS + (int64_t)id * stride;
+    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t b1 = min(n, b0 + rows_per_block);
+    const int64_t len = b1 > b0 ? b1 - b0 : 0;
+    const int64_t q = (len + ncopy - 1) / ncopy;
+    const int64_t i0 = min(b1, b0 + id * q);
+    const int64_t i1 = min(b1, i0 + q);
+    constexpr int U = 8;
+    for (int64_t ib = i0; ib < i1; ib += U) {
+        int lab[U];
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
+            v[u] = (ib + u < i1 && col < r) ? F[(ib + u) * ldf + col] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = lab[u];
+            if (c >= 0 && c < k) {
+                if (col < r) S[(int64_t)c * r + col] += (double)v[u];
+                if (col == 0) S[kr + c] += 1.0;
+            }
+        }
+    }
+    __syncthreads();
+    double *out = part + (int64_t)blockIdx.x * kr;
+    for (int64_t e = threadIdx.x; e < kr; e += blockDim.x) {
+        double a = SS[e];
+        for (int c = 1; c < ncopy; ++c) a += SS[(int64_t)c * stride + e];
+        out[e] = a;
+    }
+    for (int e = threadIdx.x; e < k; e += blockDim.x) {
+        int64_t a = 0;
+        for (int c = 0; c < ncopy; ++c) a += (int64_t)SS[(int64_t)c * stride + kr + e];
+        pcount[(int64_t)blockIdx.x * k + e] = a;
+    }
+}
+
 // same, for k*r too large for LDS: sums kept in the partial array itself
 __global__ void update_partial_global_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                              const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
@@ -655,7 +716,10 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
     constexpr int KC = 16 * NTILE;
     const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
     const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NT / 64) * 16) * rp * sizeof(float);
-    const int64_t want = (n + (NT / 64) * 16 - 1) / ((NT / 64) * 16);
+    // many small problems: about 8 row groups per wavefront, so the centroid
+    // staging of a block is spread over more rows
+    const int64_t rows_per_block = (NT / 64) * 16 * (b.count > 1 ? 8 : 1);
+    const int64_t want = (n + rows_per_block - 1) / rows_per_block;
     const int64_t cap = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
     assign_mfma_kernel<NTILE><<<grid, NT, lds, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
@@ -721,7 +785,12 @@ void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t 
     const size_t lds = ((size_t)k * r + k) * sizeof(double);
     const int threads = (int)std::min<int64_t>(256, ((r + 63) / 64) * 64);
     const dim3 g1((unsigned)nb, (unsigned)b.count);
-    if (b.count > 1 && 4 * lds <= 64 * 1024)
+    int rs = 1;
+    while (rs < r) rs *= 2;
+    if (b.count > 1 && rs <= 32 && (size_t)4 * (64 / rs) * lds <= 64 * 1024)
+        update_slots_kernel<<<g1, 256, (size_t)4 * (64 / rs) * lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount,
+                                                                          to_bat(b), rs);
+    else if (b.count > 1 && 4 * lds <= 64 * 1024)
         update_partial4_kernel<<<g1, 256, 4 * lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
     else if (lds <= 64 * 1024)
         update_partial_kernel<<<g1, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
