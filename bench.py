@@ -96,9 +96,9 @@ def extra_knn(dev):
     import torch
     import paper_1509_08863_amd as asc
     from paper_1509_08863_amd.autograd import ChebFilter, GaussWeights, RowNormLoss
-    cfg = W.CONFIGS[5]
-    seeds = W.config_seeds(5)
-    g0 = W.config_graph(5)
+    cfg = W.WORKLOADS[5]
+    seeds = W.workload_seeds(5)
+    g0 = W.workload_graph(5)
     r, p, k, sigma = cfg["r"], cfg["p"], cfg["k"], cfg["sigma"]
     out = {"workload": cfg["name"], "n": g0.n, "nnz": g0.nnz}
     for order in ("generated", "rcm"):
@@ -145,7 +145,7 @@ def extra_batch(dev):
     plan."""
     import torch
     import paper_1509_08863_amd as asc
-    cfg = W.CONFIGS[4]
+    cfg = W.WORKLOADS[4]
     r, p, steps = cfg["r"], cfg["p"], cfg["trials"]
     t0 = time.time()
     gs = W.batch_graphs()
@@ -211,12 +211,12 @@ def extra_stability(dev, c=6, reps_timed=3):
     k-means replicates; the whole sweep as one call."""
     import torch
     import paper_1509_08863_amd as asc
-    cfg = W.CONFIGS[c]
+    cfg = W.WORKLOADS[c]
     t0 = time.time()
-    g, ks, etas, J, (Rs, _), rows = W.stability_config(c)
+    g, ks, etas, J, (Rs, _), rows = W.stability_workload(c)
     gen_s = time.time() - t0
     G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev), None)
-    lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, W.config_seeds(c)["lanczos"])).to(dev), 60)
+    lmax = asc.lmax_estimate(G, torch.from_numpy(W.start_vector(g.n, W.workload_seeds(c)["lanczos"])).to(dev), 60)
     ld = (Rs.shape[1] + 3) // 4 * 4
     R = torch.zeros(g.n, ld, dtype=torch.float32, device=dev)
     R[:, :Rs.shape[1]] = torch.from_numpy(Rs).to(dev)
@@ -239,7 +239,7 @@ def extra_stability(dev, c=6, reps_timed=3):
         import oracle
         L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
         s_o = oracle.strength(g.n, g.row_ptr, g.col_idx, None)
-        lmax_o = oracle.lmax_estimate(L, s_o, W.start_vector(g.n, W.config_seeds(c)["lanczos"]), 60)
+        lmax_o = oracle.lmax_estimate(L, s_o, W.start_vector(g.n, W.workload_seeds(c)["lanczos"]), 60)
         q = len(ks) // 2
         pool = Rs[:, :eta_max].astype(np.float64)
         t0 = time.perf_counter()
@@ -258,9 +258,9 @@ def extra_small(dev):
     working set sits in L2), reported as microseconds per filter."""
     import torch
     import paper_1509_08863_amd as asc
-    cfg = W.CONFIGS[1]
-    seeds = W.config_seeds(1)
-    g = W.config_graph(1)
+    cfg = W.WORKLOADS[1]
+    seeds = W.workload_seeds(1)
+    g = W.workload_graph(1)
     G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev),
                           torch.from_numpy(g.weights_or_ones()).to(dev))
     R = torch.from_numpy(W.signals(g.n, cfg["r"], seeds["signals"])[0]).to(dev)
@@ -292,9 +292,9 @@ def extra_mid(dev):
     64 MiB buffer (cache-resident) as well as with the HBM peak."""
     import torch
     import paper_1509_08863_amd as asc
-    cfg = W.CONFIGS[2]
-    seeds = W.config_seeds(2)
-    g = W.config_graph(2)
+    cfg = W.WORKLOADS[2]
+    seeds = W.workload_seeds(2)
+    g = W.workload_graph(2)
     G = asc.graph_prepare(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col_idx).to(dev),
                           torch.from_numpy(g.weights_or_ones()).to(dev))
     r, p = cfg["r"], cfg["p"]
@@ -329,12 +329,12 @@ def extra_knn_build(dev, n=200_000, d=16, k=10):
     all pairs, float64 selection, union graph; then Gaussian weights."""
     import torch
     import paper_1509_08863_amd as asc
-    x, _ = W.gmm_points(n, d, 20, W.config_seeds(5)["graph"])
+    x, _ = W.gmm_points(n, d, 20, W.workload_seeds(5)["graph"])
     X = torch.from_numpy(x.astype(np.float32)).to(dev)
     out = asc.knn_graph(X, k)
     ms = _time(lambda: asc.knn_graph(X, k), 3)
     t0 = time.time()
-    W.gmm_knn(n, d, 20, k, W.config_seeds(5)["graph"])
+    W.gmm_knn(n, d, 20, k, W.workload_seeds(5)["graph"])
     host_s = time.time() - t0
     import oracle
     t0 = time.time()
@@ -352,7 +352,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=3, choices=[2, 3])
+    ap.add_argument("--workload", type=int, default=3, choices=[2, 3],
+                    help="3: the 1e6-node SBM (R = 96, p = 150); 2: the 1e5-node SBM (R = 64, p = 100)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
     ap.add_argument("--no-bf16", action="store_true")
@@ -398,10 +399,10 @@ def main():
     if args.stability_only:
         print(json.dumps(extra_stability(dev, args.stability_only)))
         return
-    cfg = W.CONFIGS[args.config]
-    seeds = W.config_seeds(args.config)
+    cfg = W.WORKLOADS[args.workload]
+    seeds = W.workload_seeds(args.workload)
     t0 = time.time()
-    g = W.config_graph(args.config)
+    g = W.workload_graph(args.workload)
     _progress(f"graph {cfg['name']}: n={g.n} nnz={g.nnz}")
     n, nnz, r, p, k = g.n, g.nnz, cfg["r"], cfg["p"], cfg["k"]
     steps_dich, km_iters = cfg["steps"], cfg["kmeans_iters"]

@@ -100,7 +100,7 @@ def test_batch_graph_replays_equal_eager():
 
 
 def test_batch_single_graph_equals_single_graph_api():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     big, off = W.concat_graphs([g])
     G = upload_graph(big)
     r, p, steps, k = 32, 50, 12, 10

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def test_captured_filter_replays_match_eager():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     Rs, _ = W.signals(g.n, 32, 21)
     R = block_f32(Rs)
@@ -40,7 +40,7 @@ def test_captured_filter_replays_match_eager():
 
 
 def test_captured_lambda_k_filter_replays_match_eager():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     Rs, _ = W.signals(g.n, 32, 22)
     R = block_f32(Rs)

@@ -24,7 +24,7 @@ def _setup(g, p):
 @pytest.mark.parametrize("p", [0, 1, 2, 5, 50, 51])
 @pytest.mark.parametrize("r", [4, 32, 33])
 def test_moments_match_oracle(p, r):
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L, lmax = _setup(g, p)
     G = upload_graph(g)
     Rs, R64 = W.signals(g.n, r, 11)
@@ -41,7 +41,7 @@ def test_moments_match_oracle(p, r):
 
 def test_dichotomy_on_oracle_moments_is_exact():
     # identical float64 moments in -> identical bisection decisions
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L, lmax = _setup(g, 50)
     R64 = W.signals(g.n, 32, 4)[1]
     mu = oracle.moments(L, lmax, 50, R64)
@@ -65,7 +65,7 @@ def _traj_agree(traj, traj_ref, k, tol):
 
 @pytest.mark.parametrize("literal", [False, True])
 def test_lambda_k_matches_oracle(literal):
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L, lmax = _setup(g, 50)
     G = upload_graph(g)
     Rs, R64 = W.signals(g.n, 32, 6)
@@ -139,7 +139,7 @@ def test_kmeans_init_rows():
 
 @pytest.mark.parametrize("r,p", [(32, 50), (33, 51), (8, 1)])
 def test_one_pass_lambda_k_filter(r, p):
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L, lmax = _setup(g, p)
     G = upload_graph(g)
     Rs, R64 = W.signals(g.n, r, 13)

@@ -28,7 +28,7 @@ def _oracle_setup(g, r, seed, p, frac=0.17, w=None):
 
 
 GRAPHS = {
-    "sbm_c1": lambda: W.config_graph(1),
+    "sbm_c1": lambda: W.workload_graph(1),
     "weighted_isolated": lambda: W.random_weighted(700, 0.02, 3, isolated=9),
     "path": lambda: W.path(50),
     "single_node_pairs": lambda: W.from_edges(5, [(0, 1)]),
@@ -127,7 +127,7 @@ def test_filter_bf16_parity(name, r, p):
 
 
 def test_filter_wide_leading_dimension_and_unit_weights_path():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     Y1, Yref = _run_filter_case(g, 20, 40, "f32", weighted=False, ld=40)
     Y2, _ = _run_filter_case(g, 20, 40, "f32", weighted=True, ld=24)
     assert rel_fro(Y1, Yref) <= TOL_F32
@@ -144,7 +144,7 @@ def test_filter_mid_size_sbm():
 
 def test_all_pass_is_identity():
     # cut-off at lambda_max: a = (1, 0, ..., 0) exactly -> Y = R bit for bit
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     Rs, _ = W.signals(g.n, 32, 1)
     lmax = scalar(40.0)
@@ -155,7 +155,7 @@ def test_all_pass_is_identity():
 
 def test_constant_vector_gain():
     # L 1 = 0: the constant signal is multiplied by p(-1) = sum_j a_j (-1)^j
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     lmax = 40.0
     a = oracle.cheb_coeffs(0.17 * lmax, lmax, 100)
@@ -165,7 +165,7 @@ def test_constant_vector_gain():
 
 
 def test_lmax_too_small_is_flagged():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, g.weights_or_ones().astype(np.float64))
     lam_n = oracle.lambda_max_exact(L)
@@ -181,7 +181,7 @@ def test_lmax_too_small_is_flagged():
 
 
 def test_nan_is_flagged():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     Rs, _ = W.signals(g.n, 8, 1)
     Rs[17, 3] = np.nan
@@ -193,7 +193,7 @@ def test_nan_is_flagged():
 
 
 def test_filter_deterministic():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     Rs, _ = W.signals(g.n, 32, 2)
     a = to_dev(oracle.cheb_coeffs(5.0, 40.0, 50))
@@ -231,7 +231,7 @@ def test_every_tuned_configuration_is_parity_green(dtype):
 
 
 def test_tune_table_roundtrip(tmp_path):
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     asc.tune_set(G, 32, torch.float32, 16, 1)
     path = str(tmp_path / "tune.json")

@@ -31,9 +31,9 @@ def _upload(g, w=None):
 
 
 def test_sbm_1e6_filter_sampled_columns_and_eigcount_properties():
-    cfg = W.CONFIGS[3]
-    seeds = W.config_seeds(3)
-    g = W.config_graph(3)
+    cfg = W.WORKLOADS[3]
+    seeds = W.workload_seeds(3)
+    g = W.workload_graph(3)
     r, p, k, steps = cfg["r"], cfg["p"], cfg["k"], cfg["steps"]
     G = _upload(g)
     Rs, R64 = W.signals(g.n, r, seeds["signals"])
@@ -70,9 +70,9 @@ def test_sbm_1e6_filter_sampled_columns_and_eigcount_properties():
 
 
 def test_sbm_1e5_pipeline_full_parity():
-    cfg = W.CONFIGS[2]
-    seeds = W.config_seeds(2)
-    g = W.config_graph(2)
+    cfg = W.WORKLOADS[2]
+    seeds = W.workload_seeds(2)
+    g = W.workload_graph(2)
     r, p, k, steps, iters = cfg["r"], cfg["p"], cfg["k"], cfg["steps"], cfg["kmeans_iters"]
     G = _upload(g)
     Rs, R64 = W.signals(g.n, r, seeds["signals"])
@@ -124,9 +124,9 @@ def test_sbm_1e5_pipeline_full_parity():
 
 
 def test_knn_2e5_gradients_sampled_entries():
-    cfg = W.CONFIGS[5]
-    seeds = W.config_seeds(5)
-    g = W.config_graph(5)
+    cfg = W.WORKLOADS[5]
+    seeds = W.workload_seeds(5)
+    g = W.workload_graph(5)
     r, p, sigma = cfg["r"], cfg["p"], cfg["sigma"]
     d2 = to_dev(g.d2)
     w = asc.gauss_weights(d2, sigma)
@@ -163,7 +163,7 @@ def test_knn_2e5_gradients_sampled_entries():
 
 
 def test_batch_64_graphs_full_size_sampled_graphs():
-    cfg = W.CONFIGS[4]
+    cfg = W.WORKLOADS[4]
     r, p, steps = cfg["r"], cfg["p"], cfg["trials"]
     gs = W.batch_graphs()
     ks = np.array([g.k for g in gs], dtype=np.int32)

@@ -74,7 +74,7 @@ def test_knn_nonfinite_point_is_isolated():
 def test_knn_full_size_gaussian_mixture_and_weights():
     # the gradient workload's point set: 2e5 points of a 16-D, 20-component
     # mixture, K = 10; the oracle proposes with a k-d tree and decides in float64
-    x, _ = W.gmm_points(200_000, 16, 20, W.config_seeds(5)["graph"])
+    x, _ = W.gmm_points(200_000, 16, 20, W.workload_seeds(5)["graph"])
     X = x.astype(np.float32)
     ref = oknn.knn(X, 10)
     out = _check(X, 10, ref)

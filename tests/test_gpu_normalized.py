@@ -18,7 +18,7 @@ def _ln(g):
 
 
 @pytest.mark.parametrize("make", [lambda: W.random_weighted(700, 0.02, 3, isolated=5),
-                                  lambda: W.config_graph(1), lambda: W.cliques(6, 15, bridges=True)])
+                                  lambda: W.workload_graph(1), lambda: W.cliques(6, 15, bridges=True)])
 def test_normalized_weights_and_filter(make):
     g = make()
     G = upload_graph(g)
@@ -41,7 +41,7 @@ def test_normalized_weights_and_filter(make):
 
 
 def test_normalized_lmax_estimate_and_lambda_k():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     Gn = asc.graph_normalized(upload_graph(g))
     Ln = _ln(g)
     lam = np.linalg.eigvalsh(Ln.toarray())

@@ -49,7 +49,7 @@ def test_lambda_k_filter_with_the_order_from_the_table():
     # the table feeds p (note on m, Sec. 2.4): lambda_k from the moment
     # dichotomy, p = m*(lambda_k / lmax; delta) with a band of half the cut-off,
     # then the order-p filter; checked against the oracle's m* and filter
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     G = upload_graph(g)
     L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
     lmax = oracle.lmax_estimate(L, oracle.strength(g.n, g.row_ptr, g.col_idx, None), W.start_vector(g.n, 1), 60)

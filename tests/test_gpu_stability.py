@@ -147,12 +147,12 @@ def test_stability_full_benchmark_size_sampled():
     # (k, realisation) cells one by one
     import workloads as W2
     c = 6
-    cfg = W2.CONFIGS[c]
-    g, ks, etas, J, (Rs, _), rows = W2.stability_config(c)
+    cfg = W2.WORKLOADS[c]
+    g, ks, etas, J, (Rs, _), rows = W2.stability_workload(c)
     eta_max = max(etas)
     L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
     s = oracle.strength(g.n, g.row_ptr, g.col_idx, None)
-    lmax = oracle.lmax_estimate(L, s, W2.start_vector(g.n, W2.config_seeds(c)["lanczos"]), 60)
+    lmax = oracle.lmax_estimate(L, s, W2.start_vector(g.n, W2.workload_seeds(c)["lanczos"]), 60)
     G = upload_graph(g)
     out = asc.stability(G, scalar(lmax), ks[0], ks[-1], etas, J, cfg["reps"], cfg["p"], cfg["steps"],
                         cfg["kmeans_iters"], block_f32(Rs), eta_max, to_dev(rows))

@@ -74,7 +74,7 @@ def test_cheb_eval_vs_recurrence():
     np.testing.assert_allclose(oracle.cheb_eval(a, x), ref, atol=1e-12)
 
 
-@pytest.mark.parametrize("make", [lambda: W.random_weighted(50, 0.2, 1), lambda: W.config_graph(1),
+@pytest.mark.parametrize("make", [lambda: W.random_weighted(50, 0.2, 1), lambda: W.workload_graph(1),
                                   lambda: W.cliques(4, 6, True), lambda: W.random_weighted(30, 0.2, 5, isolated=4)])
 @pytest.mark.parametrize("p", [0, 1, 2, 17, 50])
 def test_recurrence_equals_dense_matrix_polynomial(make, p):
@@ -92,7 +92,7 @@ def test_recurrence_equals_dense_matrix_polynomial(make, p):
 
 def test_spectral_error_identity():
     # |Y - H R|_F^2 = sum_l (p(x_l) - h(lambda_l))^2 |chi_l^T R|^2 (exact, Sec. 3.1 projector)
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L = _L(g)
     lam, chi = oracle.dense_spectrum(L.toarray())
     lmax = lam[-1] * 1.01
@@ -133,7 +133,7 @@ def test_disjoint_cliques_projector():
 @pytest.mark.parametrize("p", [50, 100, 150])
 def test_constant_vector_gain(p):
     # L 1 = 0 -> x = -1 -> Y(1) = p(-1) 1, p(-1) = sum_j a_j (-1)^j (close to 1)
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L = _L(g)
     lmax = 40.0
     a = oracle.cheb_coeffs(0.17 * lmax, lmax, p)

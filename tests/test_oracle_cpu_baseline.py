@@ -18,7 +18,7 @@ def _built():
 @pytest.mark.parametrize("p", [0, 1, 2, 50])
 @pytest.mark.parametrize("weighted", [False, True])
 def test_c_baseline_matches_oracle(p, weighted):
-    g = W.random_weighted(300, 0.03, 4, isolated=5) if weighted else W.config_graph(1)
+    g = W.random_weighted(300, 0.03, 4, isolated=5) if weighted else W.workload_graph(1)
     w = g.w.astype(np.float64) if weighted else None
     L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w)
     lmax = 1.01 * oracle.lambda_max_exact(L)

@@ -27,7 +27,7 @@ def test_identity_block_gives_exact_trace():
 
 
 def test_moments_route_equals_literal_route():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L = _L(g)
     lmax = 31.0
     R = W.signals(g.n, 32, 5)[1]
@@ -83,7 +83,7 @@ def test_large_gap_count_and_dichotomy():
 
 
 def test_dichotomy_literal_equals_moments_branching():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L = _L(g)
     lmax = 31.0
     R = W.signals(g.n, 32, 9)[1]

@@ -88,7 +88,7 @@ def test_check_graph_rejects():
 
 @pytest.mark.parametrize("make", [lambda: W.complete(7), lambda: W.cycle(10), lambda: W.path(9),
                                   lambda: W.star(6), lambda: W.random_weighted(60, 0.1, 4, isolated=2),
-                                  lambda: W.config_graph(1)])
+                                  lambda: W.workload_graph(1)])
 def test_lanczos_lmax(make):
     g = make()
     L = _L(g)
@@ -107,7 +107,7 @@ def test_lanczos_lmax(make):
 
 def test_lmax_unweighted_lower_bound():
     # for unit weights lambda_N >= d_max + 1 (any graph with an edge)
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     L = _L(g)
     lam, _ = oracle.dense_spectrum(L.toarray())
     dmax = np.diff(g.row_ptr).max()

@@ -18,11 +18,11 @@ def _check_csr(g):
 
 
 def test_sbm_c1_shape_and_determinism():
-    g = W.config_graph(1)
+    g = W.workload_graph(1)
     _check_csr(g)
     assert g.n == 1000
     assert 14 < g.nnz / g.n < 18           # mean degree 16
-    h = W.config_graph(1)
+    h = W.workload_graph(1)
     assert np.array_equal(g.col_idx, h.col_idx)
     # intra-community edges dominate: eps = 0.1 -> p_out/p_in = 0.1
     rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))

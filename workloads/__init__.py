@@ -31,7 +31,7 @@ def rng_for(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(int(seed)))
 
 
-def config_seeds(c: int) -> dict:
+def workload_seeds(c: int) -> dict:
     """Seeds of workload configuration c (1-based): graph, signals, k-means init, target."""
     b = BASE_SEED + 10 * c
     return {"graph": b, "signals": b + 1, "kmeans": b + 2, "target": b + 3, "lanczos": b + 4}
@@ -341,8 +341,8 @@ def unit_rows(n: int, r: int, seed: int) -> np.ndarray:
 # the benchmarked configurations
 # ---------------------------------------------------------------------------
 
-def config_graph(c: int) -> Graph:
-    s = config_seeds(c)
+def workload_graph(c: int) -> Graph:
+    s = workload_seeds(c)
     if c == 1:
         return sbm(equal_sizes(1000, 10), 16.0, 0.1, s["graph"])
     if c == 2:
@@ -354,7 +354,7 @@ def config_graph(c: int) -> Graph:
     raise ValueError(c)
 
 
-CONFIGS = {
+WORKLOADS = {
     1: dict(name="sbm_n1e3_k10_d16_r32_p50", n=1000, k=10, r=32, p=50),
     2: dict(name="sbm_n1e5_k20_d20_r64_p100", n=100_000, k=20, r=64, p=100, steps=12, kmeans_iters=10),
     3: dict(name="sbm_n1e6_k50dir_d30_r96_p150", n=1_000_000, k=50, r=96, p=150, steps=12, kmeans_iters=10),
@@ -369,10 +369,10 @@ CONFIGS = {
 }
 
 
-def stability_config(c: int):
+def stability_workload(c: int):
     """(graph, ks, etas, J, pools (float32, float64), init rows) of a stability configuration."""
-    cfg = CONFIGS[c]
-    s = config_seeds(c)
+    cfg = WORKLOADS[c]
+    s = workload_seeds(c)
     g = gmm2d_knn(cfg["n"], cfg["k_true"], s["graph"])
     ks = cfg["ks"]
     etas = [2 * k for k in ks]
