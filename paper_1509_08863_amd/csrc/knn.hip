@@ -172,7 +172,8 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
             const int64_t j = c0 + p;
             xs[p * DP + c] = (j < n && c < d) ? X[j * ldx + c] : 0.0f;
         }
-        for (int p = threadIdx.x; p < CB; p += NT) ns[p] = (c0 + p < n) ? nrm[c0 + p] : 0.0f;
+        // rows past n: +inf norm, so their distances are +inf and never proposed
+        for (int p = threadIdx.x; p < CB; p += NT) ns[p] = (c0 + p < n) ? nrm[c0 + p] : __builtin_inff();
         __syncthreads();
         const int pend = (int)min<int64_t>(CB, n - c0);
         // software pipeline: the MFMAs of tile t + 16 are issued before the
@@ -193,16 +194,20 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
         };
         // candidate indices in 32 bits (n < 2^31); two tiles per iteration so
         // the pipelined accumulators alternate instead of being copied
-        const int ni = (int)n;
+        // a tile's four values of a group are compared with the current H-th
+        // proposal at once, since most tiles bring none; the query itself is
+        // skipped there (rows past n have +inf distances)
         auto consume = [&](int t, const v4f (&acc)[2]) {
             const int j0 = (int)c0 + t + 4 * lk;
 #pragma unroll
-            for (int g = 0; g < 2; ++g)
+            for (int g = 0; g < 2; ++g) {
+                const float m = fminf(fminf(acc[g][0], acc[g][1]), fminf(acc[g][2], acc[g][3]));
+                if (m < hd[g][H - 1]) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int j = j0 + v;
-                    if (j < ni && j != qi[g]) propose(hd[g], hj[g], acc[g][v], j);
+                    for (int v = 0; v < 4; ++v)
+                        if (j0 + v != qi[g]) propose(hd[g], hj[g], acc[g][v], j0 + v);
                 }
+            }
         };
         tile_mfma(0, cur);
         for (int t = 0; t < pend; t += 32) {
@@ -258,7 +263,8 @@ __global__ __launch_bounds__(NT) void knn_exact_kernel(const float *__restrict__
     const int j = lane < NCAND ? cand_j[i * NCAND + lane] : -1;
     const float gd = lane < NCAND ? cand_d[i * NCAND + lane] : __builtin_inff();
     const double de = j >= 0 ? exact_d2(X, ldx, d, i, j) : __builtin_huge_val();
-    const bool valid = j >= 0 && de < __builtin_huge_val();  // NaN (non-finite coordinates) is no candidate
+    // the point itself and NaN (non-finite coordinates) are no candidates
+    const bool valid = j >= 0 && j != (int)i && de < __builtin_huge_val();
     // the least H-th proposal over the lane classes (+inf: that class is complete)
     float cut = (lane < NCAND && lane % H == H - 1) ? (j >= 0 ? gd : __builtin_inff()) : __builtin_inff();
     for (int off = 32; off > 0; off >>= 1) cut = fminf(cut, __shfl_xor(cut, off, 64));
