@@ -113,3 +113,28 @@ def test_multi_panel_autotune_and_workspace():
     Y = host(asc.cheb_filter(G, scalar(lmax), to_dev(a), Rd))
     assert rel_fro(Y, oracle.cheb_filter(L, lmax, a, R64)) <= 1e-5
     asc.tune_set(G, 96, torch.float32, 0, 0)
+
+
+@pytest.mark.parametrize("r,dtype,rs,var", [CASES[0], CASES[2]])
+def test_multi_panel_strided_checkpoints_and_adjoint(r, dtype, rs, var):
+    # checkpoints every 3 steps (row-major blocks, columns c0 + q RS of each
+    # slice) written by one launch over all slices equal those of one launch
+    # per slice, and so does the adjoint that recomputes from them
+    g, G, L, lmax, Rd, R64 = _setup(r, dtype, seed=9)
+    p = 20
+    a = oracle.cheb_coeffs(0.15 * lmax, lmax, p)
+    ad, lm = to_dev(a), scalar(lmax)
+    Gr = block_f32(W.signals_f64(g.n, r, 12).astype(np.float32))
+
+    def run(v):
+        def go():
+            Y, ck = asc.cheb_filter(G, lm, ad, Rd, ckpt_stride=3)
+            dW, dc = asc.cheb_filter_bwd(G, lm, ad, Rd, ck, 3, Gr)
+            need = asc._abi.lib().asc_ckpt_bytes(G.c(), r, asc._dtype_code(Rd), p, 3)
+            return host(Y), host(ck)[:need], host(dW), host(dc)
+        return _with_plan(G, r, dtype, rs, v, go)
+
+    one, multi = run(var & 7), run(var)
+    for x, y in zip(multi, one):
+        np.testing.assert_array_equal(x, y)
+    assert rel_fro(multi[0], oracle.cheb_filter(L, lmax, a, R64)) <= 1e-5
