@@ -33,6 +33,7 @@ from .cheb import (jackson, step_coeffs, cheb_coeffs, cheb_eval, cheb_filter,  #
 from .eigcount import (moments, eigcount_from_moments, eigcount_literal,  # noqa: F401
                        exact_count, dichotomy, dichotomy_moments, dichotomy_literal)
 from .cluster import normalize_rows, kmeans_assign, kmeans_update, kmeans_lloyd  # noqa: F401
+from .kmeanspp import kmeans_pp_rows  # noqa: F401
 from .grad import (gauss_weights, rownorm_loss_grad, cheb_filter_adjoint,  # noqa: F401
                    daleckii_krein_M, dW_from_M, dsigma, loss_of_weights, cheb_filter_adjoint_sampled)
 from .stability import (contingency, ari_terms, ari, ari_pairs, gamma, inertia,  # noqa: F401

@@ -495,3 +495,10 @@ def locality_order(g: Graph):
                 w=None if g.w is None else g.w[src], d2=None if g.d2 is None else g.d2[src],
                 labels=None if g.labels is None else g.labels[perm], k=g.k)
     return out, perm
+
+
+def seeding_draws(k: int, seed: int) -> np.ndarray:
+    """k random integers uniform in [0, 2^53) (uint64): the draws of a
+    k-means++ seeding, passed to both sides."""
+    rng = rng_for(seed)
+    return rng.integers(0, 1 << 53, size=k, dtype=np.uint64)
