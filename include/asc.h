@@ -210,6 +210,22 @@ asc_status asc_kmeans_init_rows(const float *F, int64_t n, int64_t r, int64_t ld
 asc_status asc_kmeans_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k,
                              int32_t *labels, float *dist2, void *stream);
 size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k);
+
+/* k-means++ seeding (Sec. 5 uses Matlab's k-means, whose default start draws
+ * each new centre with probability proportional to its squared distance to
+ * the nearest centre so far).  The draw is exact integer arithmetic: with
+ * D_i the least squared distance (float64, columns in order, no fused
+ * multiply-add) from row i to the rows chosen so far and the weights
+ * q_i = floor(2^30 (D_i / max_j D_j)), draw c >= 1 takes the least row i whose
+ * prefix sum q_0 + ... + q_i exceeds floor(U_c T / 2^53), T = sum_i q_i (if
+ * T = 0: row floor(U_c n / 2^53)); draw 0 takes row floor(U_0 n / 2^53).
+ * U[k] (device, uint64) are the caller's random integers, taken modulo 2^53;
+ * rows[k] (device, int32) receives the chosen rows, ready for
+ * asc_kmeans_init_rows.  F: n x r float32 (ldf), finite.  1 <= k <= min(n,
+ * 1024).  ws: asc_kmeanspp_workspace(n) bytes.  Launches 3 kernels per draw. */
+size_t asc_kmeanspp_workspace(int64_t n);
+asc_status asc_kmeanspp(const float *F, int64_t n, int64_t r, int64_t ldf, int k, const uint64_t *U, int32_t *rows,
+                        void *ws, size_t ws_bytes, void *stream);
 asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k,
                              float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
 

@@ -265,6 +265,19 @@ def kmeans_assign(F: torch.Tensor, C: torch.Tensor):
     return labels, dist2
 
 
+def kmeans_pp(F: torch.Tensor, k: int, U: torch.Tensor) -> torch.Tensor:
+    """Rows (int32 device tensor, k) chosen by the k-means++ draw with the
+    caller's 53-bit random integers U (int64 or uint64 tensor of k values)."""
+    L = _abi.lib()
+    n, r = F.shape
+    U = U.to(F.device).contiguous()
+    rows = torch.empty(k, dtype=torch.int32, device=F.device)
+    ws = workspace(L.asc_kmeanspp_workspace(n), F.device)
+    _abi.check(L.asc_kmeanspp(_ptr(F), n, r, _ld(F), k, _ptr(U), _ptr(rows), _ptr(ws), ws.numel(), _stream()))
+    kmeans_pp.last_ws = ws
+    return rows
+
+
 def kmeans_update(F: torch.Tensor, labels: torch.Tensor, C: torch.Tensor, ws: torch.Tensor | None = None):
     """Updates C (k x r float32, contiguous) in place; returns the member counts."""
     L = _abi.lib()

@@ -66,6 +66,8 @@ SIGNATURES = {
     "asc_kmeans_init_rows": (I32, [P, I64, I64, I64, P, I32, P, P]),
     "asc_kmeans_assign": (I32, [P, I64, I64, I64, P, I32, P, P, P]),
     "asc_kmeans_update_workspace": (SZ, [I64, I64, I32]),
+    "asc_kmeanspp_workspace": (SZ, [I64]),
+    "asc_kmeanspp": (I32, [P, I64, I64, I64, I32, P, P, P, SZ, P]),
     "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
     "asc_stream_copy": (I32, [P, P, SZ, P]),
     "asc_gather_probe": (I32, [P, I64, P, I64, P, P]),

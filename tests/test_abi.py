@@ -186,3 +186,16 @@ def test_gather_probe_rejects_before_launch():
     assert L.asc_gather_probe(fake, 0, fake, 5, fake, None) == _abi.ASC_ERR_INVALID
     assert L.asc_gather_probe(ctypes.c_void_p(0x1004), 10, fake, 5, fake, None) == _abi.ASC_ERR_INVALID
     assert L.asc_gather_probe(fake, 10, fake, 0, fake, None) == _abi.ASC_OK  # nothing to read, no launch
+
+
+def test_kmeanspp_rejects_before_launch():
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ws = L.asc_kmeanspp_workspace(100)
+    assert ws >= 100 * 8
+    assert L.asc_kmeanspp(fake, 100, 8, 8, 0, fake, fake, fake, ws, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeanspp(fake, 100, 8, 8, 101, fake, fake, fake, ws, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeanspp(fake, 100, 8, 8, 5, None, fake, fake, ws, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeanspp(fake, 100, 8, 8, 5, ctypes.c_void_p(0x1004), fake, fake, ws, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeanspp(fake, 100, 8, 4, 5, fake, fake, fake, ws, None) == _abi.ASC_ERR_INVALID
+    assert L.asc_kmeanspp(fake, 100, 8, 8, 5, fake, fake, fake, ws - 1, None) == _abi.ASC_ERR_WORKSPACE
