@@ -514,6 +514,10 @@ def main():
     ms_f32, stats_f32 = time_filter(R)
     ms_bf16, stats_bf16 = (None, None) if args.no_bf16 else time_filter(Rb)
     # pattern-only graph (w = NULL: unit weights, no weight stream), same plan
+    # k-means++ seeding of the same features (k draws), for callers that want
+    # it instead of the uniform initial rows the pipeline step uses
+    Ud = torch.from_numpy(W.seeding_draws(k, seeds["kmeans"]).astype(np.int64)).to(dev)
+    ms_kpp = _time(lambda: asc.kmeans_pp(Y, k, Ud), 3)
     ms_pat = None
     if not args.no_pattern:
         G_pat = asc.graph_prepare(rp, ci, None)
@@ -642,6 +646,7 @@ def main():
         "bf16": None if ms_bf16 is None else {"ms_per_filter_fwd": round(ms_bf16, 4), "gbs": round(gbs16, 2),
                                               "ms_per_filter_fwd_stats": stats_bf16},
         "components_ms": {k_: round(v, 4) for k_, v in comp.items()},
+        "kmeanspp_ms": round(ms_kpp, 3),
         "lambda_max": lmax_h,
         "lambda_k_est": lam_k_h,
         "pattern_only": None if ms_pat is None else {

@@ -222,7 +222,7 @@ size_t asc_kmeans_update_workspace(int64_t n, int64_t r, int k);
  * U[k] (device, uint64) are the caller's random integers, taken modulo 2^53;
  * rows[k] (device, int32) receives the chosen rows, ready for
  * asc_kmeans_init_rows.  F: n x r float32 (ldf), finite.  1 <= k <= min(n,
- * 1024).  ws: asc_kmeanspp_workspace(n) bytes.  Launches 3 kernels per draw. */
+ * 1024).  ws: asc_kmeanspp_workspace(n) bytes.  Launches 4 kernels per draw. */
 size_t asc_kmeanspp_workspace(int64_t n);
 asc_status asc_kmeanspp(const float *F, int64_t n, int64_t r, int64_t ldf, int k, const uint64_t *U, int32_t *rows,
                         void *ws, size_t ws_bytes, void *stream);

@@ -19,7 +19,8 @@ namespace asc {
 namespace {
 
 constexpr int NT = 256;
-constexpr int kBlocks = 1024;
+constexpr int kBlocks = 1024;       // blocks of the weight sums
+constexpr int kDistBlocks = 16384;  // blocks of the distance pass (and of its maxima)
 constexpr uint64_t kUMask = (uint64_t(1) << 53) - 1;
 
 // floor(a b / 2^53) for a < 2^53 and b < 2^63, from the 128-bit product
@@ -59,8 +60,8 @@ __global__ void pp_first_kernel(const uint64_t *__restrict__ U, int64_t n, int32
 
 // D_i = d(row i, rows[c]) (c == 0) or min(D_i, d(row i, rows[c])); per-block max
 __global__ __launch_bounds__(NT) void pp_dist_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
-                                                     const int32_t *__restrict__ rows, int c, double *__restrict__ D,
-                                                     double *__restrict__ pmax) {
+                                                     int vec4, const int32_t *__restrict__ rows, int c,
+                                                     double *__restrict__ D, double *__restrict__ pmax) {
 #pragma clang fp contract(off)
     __shared__ double red[NT / 64];
     const float *x = F + (int64_t)rows[c] * ldf;
@@ -68,10 +69,26 @@ __global__ __launch_bounds__(NT) void pp_dist_kernel(const float *__restrict__ F
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const float *f = F + i * ldf;
         double d = 0.0;
-        for (int64_t col = 0; col < r; ++col) {
-            const double diff = (double)f[col] - (double)x[col];
-            const double sq = diff * diff;
-            d = d + sq;
+        if (vec4) {  // 16-byte loads, the same columns in the same order
+            const float4 *f4 = reinterpret_cast<const float4 *>(f);
+            const float4 *x4 = reinterpret_cast<const float4 *>(x);
+            for (int64_t q = 0; q < r / 4; ++q) {
+                const float4 a = f4[q], b = x4[q];
+                const double d0 = (double)a.x - (double)b.x, s0 = d0 * d0;
+                d = d + s0;
+                const double d1 = (double)a.y - (double)b.y, s1 = d1 * d1;
+                d = d + s1;
+                const double d2 = (double)a.z - (double)b.z, s2 = d2 * d2;
+                d = d + s2;
+                const double d3 = (double)a.w - (double)b.w, s3 = d3 * d3;
+                d = d + s3;
+            }
+        } else {
+            for (int64_t col = 0; col < r; ++col) {
+                const double diff = (double)f[col] - (double)x[col];
+                const double sq = diff * diff;
+                d = d + sq;
+            }
         }
         const double v = (c == 0 || d < D[i]) ? d : D[i];
         D[i] = v;
@@ -87,12 +104,17 @@ __global__ __launch_bounds__(NT) void pp_dist_kernel(const float *__restrict__ F
     }
 }
 
+// dmax[0] = the largest of the distance pass's block maxima
+__global__ __launch_bounds__(NT) void pp_max_kernel(const double *__restrict__ pmax, int np, double *__restrict__ dmax) {
+    const double m = block_max(pmax, np);
+    if (threadIdx.x == 0) dmax[0] = m;
+}
+
 // bsum[b] = sum of q_i over rows [b R, min(n, (b + 1) R))
 __global__ __launch_bounds__(NT) void pp_wsum_kernel(const double *__restrict__ D, int64_t n, int64_t R,
-                                                     const double *__restrict__ pmax, int np,
-                                                     int64_t *__restrict__ bsum) {
+                                                     const double *__restrict__ dmaxp, int64_t *__restrict__ bsum) {
     __shared__ int64_t red[NT / 64];
-    const double dmax = block_max(pmax, np);
+    const double dmax = dmaxp[0];
     const int64_t i0 = (int64_t)blockIdx.x * R, i1 = min(n, i0 + R);
     int64_t s = 0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) s += pp_weight(D[i], dmax);
@@ -108,14 +130,14 @@ __global__ __launch_bounds__(NT) void pp_wsum_kernel(const double *__restrict__ 
 
 // one block: the row of draw c
 __global__ __launch_bounds__(NT) void pp_pick_kernel(const double *__restrict__ D, int64_t n, int64_t R, int nb,
-                                                     const double *__restrict__ pmax, int np,
+                                                     const double *__restrict__ dmaxp,
                                                      const int64_t *__restrict__ bsum, const uint64_t *__restrict__ U,
                                                      int c, int32_t *__restrict__ rows) {
     __shared__ int64_t scan[NT];
     __shared__ int64_t sh_base;
     __shared__ int sh_block;
     __shared__ int sh_found;
-    const double dmax = block_max(pmax, np);
+    const double dmax = dmaxp[0];
     const uint64_t u = U[c] & kUMask;
     if (threadIdx.x == 0) {
         int64_t T = 0;
@@ -173,7 +195,8 @@ using namespace asc;
 extern "C" size_t asc_kmeanspp_workspace(int64_t n) {
     Arena a(nullptr);
     a.take<double>(n > 0 ? (size_t)n : 1);  // D
-    a.take<double>(kBlocks);                // per-block maxima
+    a.take<double>(kDistBlocks);            // per-block maxima of the distance pass
+    a.take<double>(1);                      // their maximum
     a.take<int64_t>(kBlocks);               // per-block weight sums
     return a.size();
 }
@@ -190,18 +213,23 @@ extern "C" asc_status asc_kmeanspp(const float *F, int64_t n, int64_t r, int64_t
     hipStream_t s = as_stream(stream);
     Arena a(ws);
     double *D = a.take<double>((size_t)n);
-    double *pmax = a.take<double>(kBlocks);
+    double *pmax = a.take<double>(kDistBlocks);
+    double *dmax = a.take<double>(1);
     int64_t *bsum = a.take<int64_t>(kBlocks);
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kBlocks, (n + NT - 1) / NT));
     const int64_t R = (n + nb - 1) / nb;
+    const int nd = (int)std::max<int64_t>(1, std::min<int64_t>(kDistBlocks, (n + NT - 1) / NT));
+    const int vec4 = (r % 4 == 0 && ldf % 4 == 0 && aligned(F, 16)) ? 1 : 0;
     pp_first_kernel<<<1, 64, 0, s>>>(U, n, rows);
     ASC_LAUNCHED();
     for (int c = 0; c + 1 < k; ++c) {
-        pp_dist_kernel<<<nb, NT, 0, s>>>(F, n, r, ldf, rows, c, D, pmax);
+        pp_dist_kernel<<<nd, NT, 0, s>>>(F, n, r, ldf, vec4, rows, c, D, pmax);
         ASC_LAUNCHED();
-        pp_wsum_kernel<<<nb, NT, 0, s>>>(D, n, R, pmax, nb, bsum);
+        pp_max_kernel<<<1, NT, 0, s>>>(pmax, nd, dmax);
         ASC_LAUNCHED();
-        pp_pick_kernel<<<1, NT, 0, s>>>(D, n, R, nb, pmax, nb, bsum, U, c + 1, rows);
+        pp_wsum_kernel<<<nb, NT, 0, s>>>(D, n, R, dmax, bsum);
+        ASC_LAUNCHED();
+        pp_pick_kernel<<<1, NT, 0, s>>>(D, n, R, nb, dmax, bsum, U, c + 1, rows);
         ASC_LAUNCHED();
     }
     return ASC_OK;
