@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict
 }
 
 // k-means assignment on the matrix cores (2 <= k <= 16 NTILE; the centroids
-// and each wavefront's 16 rows are staged in LDS).  A wavefront takes 16
+// are staged in LDS, and up to 32 centroids the rows too).  A wavefront takes 16
 // rows: v_mfma_f32_16x16x4f32 forms the dot products with the centroids as
 // the A operand and the rows as the B operand, so lane l holds row l % 16 and
 // centroids 16 T + 4 (l / 16) + v (v = 0..3) of tile T; the approximate
@@ -255,7 +255,8 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     double *cn = lds_d;                                   // |c|^2, KC values
     double *cs = lds_d + KC;                              // |c|, KC values
     float *Cs = reinterpret_cast<float *>(lds_d + 2 * KC);  // [KC][RP], zero-padded
-    float *Fs = Cs + KC * RP + (threadIdx.x >> 6) * 16 * RP;  // this wavefront's 16 rows
+    constexpr bool kStageRows = NTILE <= 2;
+    float *Fs = Cs + KC * RP + (threadIdx.x >> 6) * 16 * RP;  // this wavefront's rows (staged only)
     F += fblk(bt);
     Cg += blockIdx.y * bt.c;
     labels += blockIdx.y * bt.l;
@@ -285,15 +286,21 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     for (int64_t g = wave0; g * 16 < n; g += nwaves) {
         const int64_t row = g * 16 + li;
         const bool live = row < n;
-        // the wavefront's 16 rows into its own LDS rows, with coalesced loads
-        // (zeros past n and past r)
-        for (int q = lane; q < 16 * RP; q += 64) {
-            const int rl = q / RP, col = q - rl * RP;
-            const int64_t rr = g * 16 + rl;
-            Fs[q] = (rr < n && col < r) ? F[rr * ldf + col] : 0.0f;
+        // up to 32 centroids the wavefront's 16 rows are staged in its own LDS
+        // rows with coalesced loads (little matrix work per column step to
+        // hide the loads behind); above, each lane reads its row from F
+        const float *fr;
+        if constexpr (kStageRows) {
+            for (int q = lane; q < 16 * RP; q += 64) {
+                const int rl = q / RP, col = q - rl * RP;
+                const int64_t rr = g * 16 + rl;
+                Fs[q] = (rr < n && col < r) ? F[rr * ldf + col] : 0.0f;
+            }
+            __builtin_amdgcn_wave_barrier();
+            fr = Fs + li * RP;
+        } else {
+            fr = F + (live ? row : 0) * ldf;
         }
-        __builtin_amdgcn_wave_barrier();
-        const float *fr = Fs + li * RP;
         v4f acc[NTILE];
 #pragma unroll
         for (int t = 0; t < NTILE; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
 #pragma unroll 4
         for (int st = 0; st < steps; ++st) {
             const int col = 4 * st + lk;
-            const float b = fr[col];
+            const float b = (live && col < r) ? fr[col] : 0.0f;
             nf += (double)b * (double)b;
 #pragma unroll
             for (int t = 0; t < NTILE; ++t) {
@@ -392,7 +399,7 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
             if (dist2) dist2[row] = (float)ed;
             if (dist64) dist64[row] = ed;
         }
-        __builtin_amdgcn_wave_barrier();  // every lane is done with Fs before the next rows
+        if constexpr (kStageRows) __builtin_amdgcn_wave_barrier();  // Fs is free for the next rows
     }
 }
 
@@ -715,7 +722,7 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
                  float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
     constexpr int KC = 16 * NTILE;
     const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
-    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NT / 64) * 16) * rp * sizeof(float);
+    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NTILE <= 2 ? (NT / 64) * 16 : 0)) * rp * sizeof(float);
     // many small problems: about 8 row groups per wavefront, so the centroid
     // staging of a block is spread over more rows
     const int64_t rows_per_block = (NT / 64) * 16 * (b.count > 1 ? 8 : 1);
@@ -727,10 +734,12 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
 
 void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
-    // matrix cores while the centroids and 4 x 16 staged rows fit 64 KB of LDS
+    // matrix cores while the centroids (and, up to 32 centroids, 4 x 16 staged
+    // rows) fit 64 KB of LDS
     const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
     const int kc = ((k + 15) / 16) * 16;
-    if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + 64) * rpad * 4 <= 64 * 1024) {
+    const int staged = kc <= 32 ? 64 : 0;
+    if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + staged) * rpad * 4 <= 64 * 1024) {
         switch ((k + 15) / 16) {
             case 1: assign_mfma<1>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
             case 2: assign_mfma<2>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
