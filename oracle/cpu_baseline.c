@@ -66,6 +66,46 @@ int oracle_cheb_filter(int64_t n, const int32_t *rp, const int32_t *ci, const do
     return 0;
 }
 
+/* <x, y>_F of two n x r row-major blocks */
+static double dot_block(int64_t nr, const double *x, const double *y)
+{
+    double acc = 0.0;
+#pragma omp parallel for schedule(static) reduction(+:acc)
+    for (int64_t q = 0; q < nr; q++) acc += x[q] * y[q];
+    return acc;
+}
+
+/* Moments of the eigenvalue count (Sec. 3.2): mu_j = <R, T_j(Lt) R>_F for
+ * j = 0..p, by the same three-term recurrence as the filter above. */
+int oracle_cheb_moments(int64_t n, const int32_t *rp, const int32_t *ci, const double *w,
+                        double lmax, int p, const double *R, int64_t r, double *mu)
+{
+    double *s = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *t0 = (double *)malloc(sizeof(double) * (size_t)(n * r > 0 ? n * r : 1));
+    double *t1 = (double *)malloc(sizeof(double) * (size_t)(n * r > 0 ? n * r : 1));
+    if (!s || !t0 || !t1) { free(s); free(t0); free(t1); return 1; }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double acc = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; e++) acc += w ? w[e] : 1.0;
+        s[i] = acc;
+    }
+    memcpy(t0, R, sizeof(double) * (size_t)(n * r));
+    mu[0] = dot_block(n * r, R, t0);
+    double *prev = t0, *cur = t1;
+    if (p >= 1) {
+        apply(n, rp, ci, w, s, lmax, prev, NULL, cur, r, 0);
+        mu[1] = dot_block(n * r, R, cur);
+    }
+    for (int j = 1; j < p; j++) {
+        apply(n, rp, ci, w, s, lmax, cur, prev, prev, r, 1);
+        double *tmp = prev; prev = cur; cur = tmp;
+        mu[j + 1] = dot_block(n * r, R, cur);
+    }
+    free(s); free(t0); free(t1);
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
     int t = 1;

@@ -20,6 +20,13 @@ def build() -> str:
     return LIB
 
 
+def ensure_built() -> str:
+    """Builds the library if it is missing or older than its source."""
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        return build()
+    return LIB
+
+
 _lib = None
 
 
@@ -33,6 +40,9 @@ def _load():
         lib.oracle_cheb_filter.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, P, ctypes.c_int,
                                            P, ctypes.c_int64, P]
         lib.oracle_cheb_filter.restype = ctypes.c_int
+        lib.oracle_cheb_moments.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int, P,
+                                            ctypes.c_int64, P]
+        lib.oracle_cheb_moments.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_set_threads.restype = None
@@ -72,3 +82,18 @@ def cheb_filter(n, row_ptr, col_idx, w, lmax, a, R):
     if rc != 0:
         raise MemoryError("oracle CPU baseline allocation failed")
     return Y
+
+
+def cheb_moments(n, row_ptr, col_idx, w, lmax, p, R):
+    """mu_j = <R, T_j(L~) R>_F, j = 0..p, in float64 (w None for unit weights)."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w64 = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    mu = np.empty(p + 1, dtype=np.float64)
+    rc = lib.oracle_cheb_moments(n, rp.ctypes.data, ci.ctypes.data, None if w64 is None else w64.ctypes.data,
+                                 float(lmax), int(p), R.ctypes.data, R.shape[1], mu.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle CPU baseline allocation failed")
+    return mu

@@ -21,7 +21,12 @@ m*(rho) = m*(1 - rho) (p for 1 - rho is 1 - p(-x) since g_0 = 1, on a grid
 symmetric about 0); m* = 1 for delta >= 1 (Jackson-damped step approximations
 stay in [0, 1]); monotonicity in delta and in w; the definition itself
 (E_{m*} <= delta < E_{m*-1}); the decay of E_m like m^-3 for a fixed band
-(the tail of the Jackson kernel), against the stalling of the undamped series.
+(the tail of the Jackson kernel), against the stalling of the undamped series;
+and the band width itself by hand-worked errors at rho = 1/2 on a 5-point grid
+(E_1 = 1/2 - 1/pi, E_2 = 1/2 - sqrt(2)/pi, m*(0.1) = 2 for w = 0.4, where the
+band |x - x_c| < w instead would give m* > 2) and by the same sup written in the
+spectral variable lambda (band |lambda - lambda_c| < w lambda_N, numpy's
+Chebyshev series) at several lambda_N.
 """
 from __future__ import annotations
 

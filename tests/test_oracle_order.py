@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from oracle import order
+from oracle import cheb, order
 
 G = 1025
 
@@ -57,3 +57,39 @@ def test_error_decays_like_inverse_cube():
     assert e[799] < e[399] < e[199] < e[99] < e[49]
     for m in (100, 200, 400, 800):
         assert 1 / 20 < e[m - 1] / e[m // 2 - 1] < 1 / 4
+
+
+def test_hand_worked_errors_and_order_pin_the_band_width():
+    # rho = 1/2 puts the jump at x_c = 0, where c_0 = 1/2, c_1 = -2/pi and
+    # c_2 = 0.  Jackson factors: g_1 = 1/2 for m = 1 (alpha = pi/3) and
+    # g_1 = 1/sqrt(2) for m = 2 (alpha = pi/4), so p_1(x) = 1/2 - x/pi and
+    # p_2(x) = 1/2 - sqrt(2) x/pi.  On the 5-point grid {+-1, +-1/sqrt(2), 0}
+    # a band of half-width w = 0.4 lambda_N (|lambda - lambda_c| < 0.4
+    # lambda_N, i.e. |x| < 0.8) keeps only x = +-1, where both errors are
+    # 1/2 - g_1 (2/pi); had the band been taken as |x| < w it would keep
+    # x = +-1/sqrt(2) too, where p_2 errs by 1/2 - 1/pi.
+    assert order.band_error(0.5, 1, 0.4, 5) == pytest.approx(0.5 - 1.0 / np.pi, abs=1e-14)
+    assert order.band_error(0.5, 2, 0.4, 5) == pytest.approx(0.5 - np.sqrt(2.0) / np.pi, abs=1e-14)
+    assert order.m_star(0.5, 0.1, 10, 0.4, 5) == 2
+    # with a band that also drops +-1/sqrt(2) only under the wrong width, the
+    # two readings part: w = 0.3 keeps |x| >= 0.6, so x = +-1/sqrt(2) counts
+    assert order.band_error(0.5, 2, 0.3, 5) == pytest.approx(0.5 - 1.0 / np.pi, abs=1e-14)
+    assert order.m_star(0.5, 0.1, 2, 0.3, 5) == 3  # none up to m = 2 meets delta
+
+
+@pytest.mark.parametrize("rho,w,m,lmax", [(0.17, 0.02, 60, 37.5), (0.05, 0.01, 150, 67.7), (0.5, 0.1, 7, 1.0),
+                                          (0.83, 0.03, 25, 12.0)])
+def test_band_error_from_the_spectrum_side(rho, w, m, lmax):
+    # the same sup written in the spectral variable lambda in [0, lambda_N]:
+    # the grid points mapped to lambda = lambda_N (x + 1) / 2, the band taken
+    # as |lambda - lambda_c| < w lambda_N with lambda_c = rho lambda_N, the
+    # ideal filter as 1[lambda <= lambda_c] and the polynomial evaluated by
+    # numpy's Chebyshev series in 2 lambda / lambda_N - 1
+    from numpy.polynomial import chebyshev
+    lam = lmax * (order.grid_points(G) + 1.0) / 2.0
+    lc = rho * lmax
+    keep = np.abs(lam - lc) >= w * lmax * (1.0 - 1e-12)
+    a = cheb.cheb_coeffs(lc, lmax, m)
+    h = (lam[keep] <= lc).astype(np.float64)
+    e_lam = float(np.max(np.abs(h - chebyshev.chebval(2.0 * lam[keep] / lmax - 1.0, a))))
+    assert order.band_error(rho, m, w, G) == pytest.approx(e_lam, abs=1e-12)
