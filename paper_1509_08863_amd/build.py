@@ -1,10 +1,12 @@
 """Builds libasc.so (the HIP library behind include/asc.h) for gfx950, in-tree.
 
-    python -m paper_1509_08863_amd.build
+    python -m paper_1509_08863_amd.build [--incremental]
 
-Every .hip under csrc/ is compiled with hipcc into build/*.o and linked into
+Every .hip under csrc/ is compiled with hipcc into _build/*.o and linked into
 paper_1509_08863_amd/libasc.so.  Packed-FP32 instruction selection is turned
-off for all device code.
+off for all device code.  With --incremental only sources newer than their
+object are recompiled (all of them if a header is newer than the oldest
+object); the default always recompiles everything.
 """
 from __future__ import annotations
 
@@ -50,11 +52,29 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _obj_of(src: str) -> str:
+    return os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+
+
+def _stale(srcs):
+    objs = [_obj_of(s) for s in srcs]
+    if not all(os.path.exists(o) for o in objs):
+        return [s for s, o in zip(srcs, objs) if not os.path.exists(o)] or srcs
+    oldest = min(os.path.getmtime(o) for o in objs)
+    headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    if any(os.path.getmtime(h) > oldest for h in headers):
+        return srcs
+    return [s for s, o in zip(srcs, objs) if os.path.getmtime(s) > os.path.getmtime(o)]
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    todo = _stale(srcs) if incremental else srcs
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(_compile, todo))
+    objs = [_obj_of(s) for s in srcs]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -67,5 +87,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -188,7 +188,9 @@ def test_sbm_1e6_fwd_bwd_sampled_against_oracle(sbm1e6):
     torch.cuda.empty_cache()
     ent = np.sort(np.random.default_rng(11).choice(g.nnz, 3000, replace=False))
     print("[fullsize] float64 sampled adjoint on 3 columns", flush=True)
-    dw_o, da_o = oracle.cheb_filter_adjoint_sampled(g.n, g.row_ptr, g.col_idx, None, lmax_o, a, R64[:, cols],
+    # unit weights (the device graph has w = NULL): the oracle takes them explicitly
+    ones = np.ones(g.nnz, dtype=np.float64)
+    dw_o, da_o = oracle.cheb_filter_adjoint_sampled(g.n, g.row_ptr, g.col_idx, ones, lmax_o, a, R64[:, cols],
                                                     Gz[:, cols].astype(np.float64), ent)
     for name, dW, dc in (("store", dW1, dc1), (f"ckpt{c}", dWc, dcc)):
         e_w, e_a = rel_fro(dW[ent], dw_o), rel_fro(dc, da_o)
