@@ -147,6 +147,29 @@ asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, const double 
                            const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
                            void *ckpt, int ckpt_stride, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * asc_cheb_filter with the same arguments, checks, kernels and results, except
+ * that the workspace is a static device array of ASC_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) inside the library instead of (ws, ws_bytes).  The array is
+ * created with the library's code object on every device the library runs
+ * on and held until the process ends; its device address is looked up once
+ * per device, on the first call with that device current.  Nothing is
+ * allocated by the call (R, Y and ckpt are still the caller's).
+ * Limit: asc_filter_workspace(n, r, sig, p) <= ASC_NOALLOC_SCRATCH_BYTES,
+ * e.g. n <= 130000 at r = 32 or n <= 86000 at r = 96 (float32); larger
+ * sizes return ASC_ERR_WORKSPACE and launch nothing.
+ * Every call on one device uses that device's one array, which keeps the
+ * last call's contents (everything a call reads from it, it first writes
+ * itself, the health flags included): calls ordered on one stream are safe,
+ * calls that overlap in time on one device (other streams, other threads)
+ * race and give wrong results.  The health flags live in the array and are
+ * not readable through asc_read_flags. */
+#define ASC_NOALLOC_SCRATCH_BYTES (64u << 20)
+asc_status asc_cheb_filter_noalloc(const asc_graph *g, const double *lmax, const double *coeffs, int p,
+                                   const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y, int64_t ldy,
+                                   void *ckpt, int ckpt_stride, void *stream);
+
 /* Sec. 3.2: Chebyshev moments mu_j = <R, T_j(Lt) R>_F, j = 0..p (float64,
  * deterministic fixed-order reductions), from ceil(p/2) recurrence steps
  * using mu_{2j} = 2 |T_j R|^2 - mu_0 and mu_{2j+1} = 2 <T_{j+1} R, T_j R> - mu_1

@@ -21,7 +21,7 @@ __all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filte
            "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
            "tune_save", "tune_load", "autotune_filter", "cheb_filter_bwd", "gauss_weights", "gauss_weights_bwd",
            "rownorm_loss_bwd", "Batch", "stream_copy",
-           "lambda_k_filter"]
+           "lambda_k_filter", "cheb_filter_noalloc"]
 
 
 def _stream():
@@ -138,6 +138,18 @@ def cheb_filter(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Ten
                                  _ptr(ck), ckpt_stride, _ptr(ws), ws.numel(), _stream()))
     cheb_filter.last_ws = ws
     return (Y, ck) if ckpt_stride else Y
+
+
+def cheb_filter_noalloc(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, Y: torch.Tensor,
+                       ckpt: torch.Tensor | None = None, ckpt_stride: int = 0) -> torch.Tensor:
+    """cheb_filter into the caller's Y with the library's static device
+    scratch as workspace (asc_cheb_filter_noalloc): allocates nothing."""
+    coeffs = coeffs.reshape(-1)
+    n, r = R.shape
+    _abi.check(_abi.lib().asc_cheb_filter_noalloc(g.c(), _ptr(lmax), _ptr(coeffs), coeffs.numel() - 1, _ptr(R),
+                                                  _dtype_code(R), r, _ld(R), _ptr(Y), _ld(Y), _ptr(ckpt),
+                                                  ckpt_stride, _stream()))
+    return Y
 
 
 def cheb_filter_bwd(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, ckpt: torch.Tensor,

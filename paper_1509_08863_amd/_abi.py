@@ -57,6 +57,7 @@ SIGNATURES = {
     "asc_lambda_k_filter_workspace": (SZ, [I64, I64, I32, I32]),
     "asc_lambda_k_filter": (I32, [GP, P, I32, I32, I32, P, I32, I64, I64, P, I64, P, P, P, P, P, SZ, P]),
     "asc_cheb_filter": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I64, P, I32, P, SZ, P]),
+    "asc_cheb_filter_noalloc": (I32, [GP, P, P, I32, P, I32, I64, I64, P, I64, P, I32, P]),
     "asc_moments_workspace": (SZ, [I64, I64, I32, I32]),
     "asc_cheb_moments": (I32, [GP, P, I32, P, I32, I64, I64, P, P, SZ, P]),
     "asc_eigcount_dichotomy": (I32, [P, I32, P, I32, I32, I32, P, P, P]),

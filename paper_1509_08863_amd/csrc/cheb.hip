@@ -399,6 +399,54 @@ extern "C" asc_status asc_cheb_filter(const asc_graph *g, const double *lmax, co
     return run_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, ckpt, ckpt_stride, ws, true, as_stream(stream));
 }
 
+// ---------------------------------------------------------------------------
+// the filter with its workspace in a static device array (no allocation)
+// ---------------------------------------------------------------------------
+// One copy per device, held until the process ends.  Host code never passes
+// the array's own name to a kernel: that is a host-side shadow, not a device
+// address; the address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[ASC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void *scratch_ptr[kMaxDevices] = {};
+
+asc_status scratch_for_current_device(void **out, const char *who) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(ASC_ERR_HIP, "%s: hipGetDevice: %s", who, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ASC_ERR_INVALID, "%s: device %d beyond %d", who, dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ASC_ERR_HIP, "%s: hipGetSymbolAddress(scratch) on device %d: %s", who, dev,
+                        hipGetErrorString(e));
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return ASC_OK;
+}
+}  // namespace
+
+extern "C" asc_status asc_cheb_filter_noalloc(const asc_graph *g, const double *lmax, const double *coeffs, int p,
+                                              const void *R, asc_dtype sig, int64_t r, int64_t ldr, float *Y,
+                                              int64_t ldy, void *ckpt, int ckpt_stride, void *stream) {
+    const char *who = "asc_cheb_filter_noalloc";
+    ASC_TRY(check_common(g, lmax, p, R, sig, r, ldr, who));
+    const size_t need = asc_filter_workspace(g->n, r, sig, p);
+    if (need > (size_t)ASC_NOALLOC_SCRATCH_BYTES)
+        return fail(ASC_ERR_WORKSPACE, "%s: n=%lld, r=%lld needs %zu bytes of scratch; the static array holds %zu",
+                    who, (long long)g->n, (long long)r, need, (size_t)ASC_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    ASC_TRY(scratch_for_current_device(&ws, who));
+    // same checks and kernels as asc_cheb_filter; the scratch is its workspace
+    return asc_cheb_filter(g, lmax, coeffs, p, R, sig, r, ldr, Y, ldy, ckpt, ckpt_stride, ws,
+                           (size_t)ASC_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 extern "C" size_t asc_moments_workspace(int64_t n, int64_t r, asc_dtype sig, int p) { return moments_ws(n, r, sig, p); }
 
 extern "C" asc_status asc_cheb_moments(const asc_graph *g, const double *lmax, int p, const void *R, asc_dtype sig,
