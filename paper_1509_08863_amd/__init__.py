@@ -153,7 +153,8 @@ def cheb_filter_noalloc(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: t
 
 
 def cheb_filter_bwd(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch.Tensor, ckpt: torch.Tensor,
-                    ckpt_stride: int, G: torch.Tensor, want_dw: bool = True, want_dcoeffs: bool = True):
+                    ckpt_stride: int, G: torch.Tensor, want_dw: bool = True, want_dcoeffs: bool = True,
+                    ws: torch.Tensor | None = None):
     """(dW per stored entry float32 or None, dcoeffs float64 or None)."""
     L = _abi.lib()
     coeffs = coeffs.reshape(-1)
@@ -162,7 +163,10 @@ def cheb_filter_bwd(g: Graph, lmax: torch.Tensor, coeffs: torch.Tensor, R: torch
     dt = _dtype_code(R)
     dW = torch.empty(g.nnz, dtype=torch.float32, device=R.device) if want_dw else None
     dc = torch.empty(p + 1, dtype=torch.float64, device=R.device) if want_dcoeffs else None
-    ws = workspace(L.asc_filter_bwd_workspace(n, g.nnz, r, dt, p, ckpt_stride), R.device)
+    need = L.asc_filter_bwd_workspace(n, g.nnz, r, dt, p, ckpt_stride)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, R.device)
+    cheb_filter_bwd.last_ws = ws
     _abi.check(L.asc_cheb_filter_bwd(g.c(), _ptr(lmax), _ptr(coeffs), p, _ptr(R), dt, r, _ld(R), _ptr(ckpt),
                                      ckpt_stride, _ptr(G), _ld(G), _ptr(dW), _ptr(dc), _ptr(ws), ws.numel(),
                                      _stream()))

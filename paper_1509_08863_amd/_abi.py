@@ -6,7 +6,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libasc.so")
+# ASC_LIBRARY names another build of the same library (the host-sanitizer
+# build the CPU tests use); by default the in-tree libasc.so
+LIB_PATH = os.environ.get("ASC_LIBRARY") or os.path.join(HERE, "libasc.so")
 
 ASC_OK = 0
 ASC_ERR_INVALID = 1

@@ -1,6 +1,6 @@
 """Builds libasc.so (the HIP library behind include/asc.h) for gfx950, in-tree.
 
-    python -m paper_1509_08863_amd.build [--incremental]
+    python -m paper_1509_08863_amd.build [--incremental | --sanitize]
 
 Every .hip under csrc/ is compiled with hipcc into _build/*.o and linked into
 paper_1509_08863_amd/libasc.so.  Packed-FP32 instruction selection is turned
@@ -86,6 +86,56 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     return LIB
 
 
+# Host-only build for the sanitizers: every source compiled for the host alone
+# (relocatable device code with no device part, so nothing is compiled for the
+# GPU and no kernel can run), with AddressSanitizer and UndefinedBehaviorSanitizer
+# on the host code, linked into _build/sanitize/libasc_sanitize.so.  Loading it
+# needs the ASan runtime preloaded; it serves the argument checks, workspace
+# sizing, planning and tuning-table code of the CPU tests.
+SANITIZE_DIR = os.path.join(BUILD, "sanitize")
+SANITIZE_LIB = os.path.join(SANITIZE_DIR, "libasc_sanitize.so")
+SANITIZE_FLAGS = [
+    f"--offload-arch={ARCH}", "-fgpu-rdc", "--offload-host-only",
+    "-O1", "-g", "-std=c++17", "-fPIC", "-fno-omit-frame-pointer",
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-I", os.path.join(ROOT, "include"),
+    "-I", CSRC,
+]
+
+
+def _compile_sanitized(src: str) -> str:
+    obj = os.path.join(SANITIZE_DIR, os.path.basename(src).replace(".hip", ".o"))
+    r = subprocess.run([HIPCC, *SANITIZE_FLAGS, "-c", src, "-o", obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (sanitize) failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build_sanitized(verbose: bool = False, incremental: bool = False) -> str:
+    os.makedirs(SANITIZE_DIR, exist_ok=True)
+    srcs = sources()
+    deps = srcs + glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    if incremental and os.path.exists(SANITIZE_LIB) and \
+            os.path.getmtime(SANITIZE_LIB) >= max(os.path.getmtime(d) for d in deps):
+        return SANITIZE_LIB
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile_sanitized, srcs))
+    tmp = SANITIZE_LIB + ".tmp"
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-fgpu-rdc", "--hip-link", "-shared", "-fPIC", *objs,
+                        "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (sanitize) failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SANITIZE_LIB)
+    if verbose:
+        print("built", SANITIZE_LIB)
+    return SANITIZE_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True, incremental="--incremental" in sys.argv[1:])
+    if "--sanitize" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -104,6 +104,14 @@ __device__ __forceinline__ float group8_reduce_scatter(const float (&p)[8], int 
     return keep + __shfl_xor(send, 1, 64);  // entry t
 }
 
+// Per-entry accumulator stores of a tile are staged in LDS and written out
+// once the whole tile is done: the 4-byte stores of a row group come one
+// neighbour group at a time, microseconds apart while the gathers are in
+// flight, and written straight to memory they leave partly written lines that
+// the L2 writes back more than once.  A tile of up to this many stored
+// entries is staged (16 KB of LDS per workgroup); longer tiles store directly.
+constexpr int kStageEntries = 4096;
+
 // PF: the next neighbour group's indices, weights and accumulated entries are
 // loaded while the current group's gathers are in flight (pays off on long
 // rows; on short rows the extra registers cost more than it hides)
@@ -138,11 +146,22 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
         tend = xcd * chunk + chunk < ntiles ? xcd * chunk + chunk : ntiles;
         tstep = (gridDim.x - xcd + 7) / 8;
     }
+    constexpr bool STAGE = (MODE & B_DW) != 0;
+    __shared__ float mstage[STAGE ? kStageEntries : 1];
     for (int64_t tile = tfirst; tile < tend; tile += tstep) {
         const int64_t row = tile * ROWS + (int64_t)wave * RPW + sub;
         // rows past n still run the neighbour loop (with no entries) so that
         // every lane takes part in the group reductions
         const bool live = row < A.n;
+        // the tile's stored entries [te0, te1) (block-uniform)
+        int32_t te0 = 0, te1 = 0;
+        if (STAGE) {
+            const int64_t r0 = tile * ROWS;
+            const int64_t r1 = r0 + ROWS < A.n ? r0 + ROWS : A.n;
+            te0 = A.rp[r0];
+            te1 = A.rp[r1];
+        }
+        const bool staged = STAGE && (te1 - te0) <= kStageEntries;
         const int64_t rrow = live ? row : 0;
         const int32_t e0 = live ? A.rp[row] : 0;
         const int32_t e1 = live ? A.rp[row + 1] : 0;
@@ -191,14 +210,20 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
                         if (u == t) own_m = mtv[u];
-                    if (e + t < e1) A.mt[e + t] = own_m + A.cj * ds;
+                    if (e + t < e1) {
+                        if (staged) mstage[e + t - te0] = own_m + A.cj * ds;
+                        else A.mt[e + t] = own_m + A.cj * ds;
+                    }
                 } else {
                     float dsum[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) dsum[u] = group_sum<LPR>(dot_raw(v[u], tv));
 #pragma unroll
                     for (int u = 0; u < U; ++u)
-                        if ((u % LPR) == t && e + u < e1) A.mt[e + u] = mtv[u] + A.cj * dsum[u];
+                        if ((u % LPR) == t && e + u < e1) {
+                            if (staged) mstage[e + u - te0] = mtv[u] + A.cj * dsum[u];
+                            else A.mt[e + u] = mtv[u] + A.cj * dsum[u];
+                        }
                 }
             }
             if (PF && e + U < e1) {
@@ -239,6 +264,12 @@ __global__ __launch_bounds__(NT) void adj_step(AdjArgs A) {
                 for (int q = 0; q < VN; ++q) nxt[q] = fmaf(aj, g[q], fmaf(d, own[q], fmaf(beta, acc[q], -old[q])));
             }
             st16(aout + row * RS + t * VN, nxt, stv);
+        }
+        if (staged) {
+            // the tile's entries, complete, in one pass of consecutive stores
+            __syncthreads();
+            for (int32_t q = (int32_t)threadIdx.x; q < te1 - te0; q += NT) A.mt[te0 + q] = mstage[q];
+            __syncthreads();
         }
     }
     if (MODE & B_DA) {

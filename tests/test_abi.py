@@ -199,3 +199,53 @@ def test_kmeanspp_rejects_before_launch():
     assert L.asc_kmeanspp(fake, 100, 8, 8, 5, ctypes.c_void_p(0x1004), fake, fake, ws, None) == _abi.ASC_ERR_INVALID
     assert L.asc_kmeanspp(fake, 100, 8, 4, 5, fake, fake, fake, ws, None) == _abi.ASC_ERR_INVALID
     assert L.asc_kmeanspp(fake, 100, 8, 8, 5, fake, fake, fake, ws - 1, None) == _abi.ASC_ERR_WORKSPACE
+
+
+def test_tuning_table_round_trip_and_file_format(tmp_path):
+    L = _abi.lib()
+    n, nnz, r = 123457, 999, 40
+    rs, var = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.asc_tune_set(n, nnz, r, 0, 16, 5) == _abi.ASC_OK
+    path = str(tmp_path / "tune.json").encode()
+    try:
+        assert L.asc_tune_save(path) == _abi.ASC_OK
+        assert L.asc_tune_set(n, nnz, r, 0, 0, 0) == _abi.ASC_OK  # slice_cols 0 erases the entry
+        assert L.asc_tune_get(n, nnz, r, 0, ctypes.byref(rs), ctypes.byref(var)) == _abi.ASC_OK
+        assert (rs.value, var.value) == (32, 0)  # the default plan for 40 float32 columns
+        assert L.asc_tune_load(path) == _abi.ASC_OK
+        assert L.asc_tune_get(n, nnz, r, 0, ctypes.byref(rs), ctypes.byref(var)) == _abi.ASC_OK
+        assert (rs.value, var.value) == (16, 5)
+        # invalid settings are rejected; a file with malformed, over-long and
+        # invalid lines loads only its valid entries
+        assert L.asc_tune_set(n, nnz, r, 0, 12, 0) == _abi.ASC_ERR_INVALID
+        assert L.asc_tune_set(n, nnz, r, 0, 16, 16) == _abi.ASC_ERR_INVALID
+        assert L.asc_tune_set(n, nnz, r, 0, 0, 0) == _abi.ASC_OK
+        bad = tmp_path / "bad.json"
+        bad.write_text("[\n" + "x" * 5000 + "\n"
+                       + '{"n": 5, "nnz": 7, "r": 40, "dtype": 0, "slice_cols": 12, "variant": 0, "ms": 1.0},\n'
+                       + '{"n": 5, "nnz": 7, "r": 40, "dtype": 3, "slice_cols": 16, "variant": 0, "ms": 1.0},\n'
+                       + '{"n": 123457, "nnz": 999, "r": 40, "dtype": 0, "slice_cols": 8, "variant": 2, "ms": 0.5}\n'
+                       + "]\n")
+        assert L.asc_tune_load(str(bad).encode()) == _abi.ASC_OK
+        assert L.asc_tune_get(n, nnz, r, 0, ctypes.byref(rs), ctypes.byref(var)) == _abi.ASC_OK
+        assert (rs.value, var.value) == (8, 2)
+        assert L.asc_tune_get(5, 7, 40, 0, ctypes.byref(rs), ctypes.byref(var)) == _abi.ASC_OK
+        assert (rs.value, var.value) == (32, 0)
+        assert L.asc_tune_load(str(tmp_path / "missing.json").encode()) == _abi.ASC_ERR_INVALID
+    finally:
+        L.asc_tune_set(n, nnz, r, 0, 0, 0)
+
+
+def test_noalloc_filter_rejects_beyond_its_scratch_before_any_device_call():
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x10000)
+    n, r, p = 200_000, 96, 10
+    assert L.asc_filter_workspace(n, r, 0, p) > (64 << 20)
+    g = _g(n, 10)
+    st = L.asc_cheb_filter_noalloc(ctypes.byref(g), fake, fake, p, fake, 0, r, r, ctypes.c_void_p(0x100000000),
+                                   r, None, 0, None)
+    assert st == _abi.ASC_ERR_WORKSPACE
+    assert b"static array" in L.asc_last_error()
+    g0 = _g(10, 0)
+    assert L.asc_cheb_filter_noalloc(ctypes.byref(g0), fake, fake, -1, fake, 0, 8, 8, fake, 8, None, 0,
+                                     None) == _abi.ASC_ERR_INVALID

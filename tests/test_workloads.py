@@ -86,3 +86,20 @@ def test_locality_order_is_a_relabelling():
     rows_g = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
     rows_h = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
     assert np.abs(rows_h - h.col_idx).mean() < 0.5 * np.abs(rows_g - g.col_idx).mean()
+
+
+def test_block_order_makes_blocks_contiguous():
+    import oracle
+    g = W.sbm(W.dirichlet_sizes(3000, 6, 5.0, 4), 12.0, 0.05, 5)
+    h, perm = W.block_order(g)
+    _check_csr(h)
+    assert sorted(perm.tolist()) == list(range(g.n))
+    # labels non-decreasing, every block one contiguous range
+    assert np.all(np.diff(h.labels) >= 0)
+    np.testing.assert_array_equal(h.labels, g.labels[perm])
+    Lg = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+    Lh = oracle.laplacian_sparse(h.n, h.row_ptr, h.col_idx, None)
+    assert abs(Lg[perm][:, perm] - Lh).max() == 0.0
+    # intra-block edges now join nearby indices: most stored entries stay in the row's block
+    rows = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+    assert np.mean(h.labels[rows] == h.labels[h.col_idx]) > 0.5

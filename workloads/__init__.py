@@ -488,13 +488,30 @@ def locality_order(g: Graph):
     from scipy.sparse.csgraph import reverse_cuthill_mckee
     A = sp.csr_matrix((np.arange(1, g.nnz + 1, dtype=np.int64), g.col_idx, g.row_ptr), shape=(g.n, g.n))
     perm = reverse_cuthill_mckee(A, symmetric_mode=True).astype(np.int64)
+    return _relabel(g, perm), perm
+
+
+def block_order(g: Graph):
+    """(permuted Graph, perm) with the nodes of each generating block (the
+    SBM's community labels) made contiguous, blocks in label order and nodes
+    in their current order inside a block (perm[new] = old).  It uses the
+    generator's own labels, i.e. the best node order any partitioner could
+    find for this graph; data-layout preprocessing only."""
+    if g.labels is None:
+        raise ValueError("block_order needs the generator's labels")
+    perm = np.argsort(g.labels, kind="stable").astype(np.int64)
+    return _relabel(g, perm), perm
+
+
+def _relabel(g: Graph, perm: np.ndarray) -> Graph:
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.arange(1, g.nnz + 1, dtype=np.int64), g.col_idx, g.row_ptr), shape=(g.n, g.n))
     B = A[perm][:, perm].tocsr()
     B.sort_indices()
     src = B.data - 1  # position of each new entry in the old arrays
-    out = Graph(n=g.n, row_ptr=B.indptr.astype(np.int32), col_idx=B.indices.astype(np.int32),
-                w=None if g.w is None else g.w[src], d2=None if g.d2 is None else g.d2[src],
-                labels=None if g.labels is None else g.labels[perm], k=g.k)
-    return out, perm
+    return Graph(n=g.n, row_ptr=B.indptr.astype(np.int32), col_idx=B.indices.astype(np.int32),
+                 w=None if g.w is None else g.w[src], d2=None if g.d2 is None else g.d2[src],
+                 labels=None if g.labels is None else g.labels[perm], k=g.k)
 
 
 def seeding_draws(k: int, seed: int) -> np.ndarray:
