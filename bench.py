@@ -793,7 +793,7 @@ def main():
     launch_ms = ms_f32 / launches
     alg_launch = bs32 / nsl
     traffic = step_traffic_bytes(cfg["name"], rs32, var32)
-    copy_big = copy_bandwidth(dev, 2 << 30, 10)
+    copy_big = copy_bandwidth(dev, 4 << 30, 10)
     copy_llc = copy_bandwidth(dev, 64 << 20, 50)
     gfloor = gather_floor_ms(dev, ci, n) if rs32 == 32 else None
     # Y moves on every other step with float32 states (a pair of terms added
@@ -925,7 +925,7 @@ def main():
                      "launches_per_filter": launches,
                      "amplification": None if traffic is None else round(traffic / alg_launch, 3),
                      "traffic_gbs": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 1),
-                     "copy_gbs_2GiB": round(copy_big["GBps"], 1), "copy_gbs_64MiB": round(copy_llc["GBps"], 1),
+                     "copy_gbs_4GiB": round(copy_big["GBps"], 1), "copy_gbs_64MiB": round(copy_llc["GBps"], 1),
                      "frac_of_copy": round(alg_launch / (launch_ms * 1e-3) / 1e9 / (copy_big["GBps"]), 4),
                      "gather_floor_ms": None if gfloor is None else round(gfloor, 5),
                      "frac_of_gather_floor": None if gfloor is None else round(gfloor / launch_ms, 4)},

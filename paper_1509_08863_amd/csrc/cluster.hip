@@ -182,7 +182,26 @@ __global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict
             double d[RB];
 #pragma unroll
             for (int q = 0; q < RB; ++q) d[q] = 0.0;
-            for (int64_t col = 0; col < r; ++col) {
+            int64_t col = 0;
+            for (; col + 4 <= r; col += 4) {
+                // four columns of every row loaded per pass, summed in column order
+                float fv[RB][4];
+#pragma unroll
+                for (int q = 0; q < RB; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) fv[q][u] = f[q][col + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double cv = Cd[(col + u) * kp + c];
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) {
+                        const double diff = (double)fv[q][u] - cv;
+                        const double sq = diff * diff;
+                        d[q] = d[q] + sq;
+                    }
+                }
+            }
+            for (; col < r; ++col) {
                 const double cv = Cd[col * kp + c];
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
@@ -305,16 +324,36 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
 #pragma unroll
         for (int t = 0; t < NTILE; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
         double nf = 0.0;
-#pragma unroll 4
-        for (int st = 0; st < steps; ++st) {
-            const int col = 4 * st + lk;
-            const float b = (live && col < r) ? fr[col] : 0.0f;
-            nf += (double)b * (double)b;
+        // four column steps per pass; the row values of the next pass are
+        // loaded while this pass's products run (the products and sums still
+        // run step by step, in column order)
+        float bv[4];
 #pragma unroll
-            for (int t = 0; t < NTILE; ++t) {
-                const float a = Cs[(16 * t + li) * RP + col];
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        for (int u = 0; u < 4; ++u) {
+            const int col = 4 * u + lk;
+            bv[u] = (live && col < r) ? fr[col] : 0.0f;
+        }
+        for (int st0 = 0; st0 < steps; st0 += 4) {
+            float bn[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int col = 4 * (st0 + 4 + u) + lk;
+                bn[u] = (live && col < r) ? fr[col] : 0.0f;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (st0 + u >= steps) break;
+                const int col = 4 * (st0 + u) + lk;
+                const float b = bv[u];
+                nf += (double)b * (double)b;
+#pragma unroll
+                for (int t = 0; t < NTILE; ++t) {
+                    const float a = Cs[(16 * t + li) * RP + col];
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[u] = bn[u];
         }
         // |f|^2 of row li: the four lanes li, li+16, li+32, li+48 hold its columns
         nf += __shfl_xor(nf, 16, 64);
@@ -372,7 +411,20 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
                 const int c = 16 * (slot >> 2) + 4 * lk + (slot & 3);
                 const float *cr = Cs + c * RP;
                 double d = 0.0;
-                for (int64_t col = 0; col < r; ++col) {
+                // eight row values loaded per pass, then summed in column order
+                int64_t col = 0;
+                for (; col + 8 <= r; col += 8) {
+                    float fv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) fv[q] = fr[col + q];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const double diff = (double)fv[q] - (double)cr[col + q];
+                        const double sq = diff * diff;
+                        d = d + sq;
+                    }
+                }
+                for (; col < r; ++col) {
                     const double diff = (double)fr[col] - (double)cr[col];
                     const double sq = diff * diff;
                     d = d + sq;
@@ -436,7 +488,20 @@ __global__ __launch_bounds__(NT) void assign_grouped_kernel(const float *__restr
         const bool valid = i < n;
         const float *f = F + (valid ? i : 0) * ldf;
         double d = 0.0;
-        for (int64_t col = 0; col < r; ++col) {
+        // eight row values loaded per pass, then summed in column order
+        int64_t col = 0;
+        for (; col + 8 <= r; col += 8) {
+            float fv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) fv[q] = f[col + q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double diff = (double)fv[q] - Cd[(col + q) * KP + c];
+                const double sq = diff * diff;
+                d = d + sq;
+            }
+        }
+        for (; col < r; ++col) {
             const double diff = (double)f[col] - Cd[col * KP + c];
             const double sq = diff * diff;
             d = d + sq;

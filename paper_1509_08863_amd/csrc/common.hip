@@ -80,9 +80,23 @@ extern "C" asc_status asc_read_flags(const void *ws, uint32_t *flags_host, void 
 // plain streaming copy (16-byte vectors), the reference kernel for bandwidth
 // and memory-counter calibration
 namespace {
-__global__ void stream_copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Four 16-byte vectors in flight per lane (all loads before the stores) and
+// non-temporal hints: the fastest of the plain copies measured on this device
+// (about 5.1 TB/s for 2 GiB, 5.3 TB/s for 4 GiB, against 4.6-4.8 TB/s for one
+// vector per lane and iteration).
+typedef unsigned cp4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_copy_kernel(const cp4 *__restrict__ src, cp4 *__restrict__ dst,
+                                                          int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        cp4 a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = __builtin_nontemporal_load(src + i + q * stride);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) __builtin_nontemporal_store(a[q], dst + i + q * stride);
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 // rows idx[e] of a table of 128-byte rows: 8 lanes per row (16 bytes each),
 // 8 rows in flight per lane group, grid-stride over the index list; indices
@@ -136,10 +150,9 @@ extern "C" asc_status asc_stream_copy(const void *src, void *dst, size_t bytes, 
     if (!src || !dst || bytes % 16 || !aligned(src, 16) || !aligned(dst, 16))
         return fail(ASC_ERR_INVALID, "asc_stream_copy: pointers must be 16-byte aligned and bytes a multiple of 16");
     const int64_t n16 = (int64_t)(bytes / 16);
-    const int grid = (int)std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    const int grid = (int)std::min<int64_t>((n16 + 255) / 256, 65536);
     if (n16 == 0) return ASC_OK;
-    stream_copy_kernel<<<grid, 256, 0, as_stream(stream)>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst),
-                                                             n16);
+    stream_copy_kernel<<<grid, 256, 0, as_stream(stream)>>>(static_cast<const cp4 *>(src), static_cast<cp4 *>(dst), n16);
     ASC_LAUNCHED();
     return ASC_OK;
 }

@@ -208,3 +208,39 @@ def test_backward_xcd_band_schedule_gives_the_same_gradients():
         asc.tune_set(Gd, r, torch.float32, 0, 0)
     np.testing.assert_array_equal(d1[0], d0[0])
     np.testing.assert_allclose(d1[1], d0[1], rtol=1e-12, atol=1e-12 * np.max(np.abs(d0[1])))
+
+
+@pytest.mark.parametrize("c", [1, 4])
+@pytest.mark.parametrize("r", [5, 40])
+def test_backward_with_tiles_too_long_to_stage(c, r):
+    # rows 0..319 form a dense block (about 160 entries per row, so each of
+    # its 32-row tiles holds more stored entries than the 4096 the adjoint
+    # stages in LDS and stores its accumulator entries directly); the other
+    # rows are sparse (staged tiles)
+    rng = np.random.default_rng(21)
+    n, nd = 2400, 320
+    iu = np.triu_indices(nd, 1)
+    keep = rng.random(iu[0].shape[0]) < 0.5
+    dense = np.stack([iu[0][keep], iu[1][keep]], 1)
+    sparse = rng.integers(0, n, size=(8 * n, 2))
+    sparse = sparse[sparse[:, 0] != sparse[:, 1]]
+    e = np.concatenate([dense, np.sort(sparse, axis=1)])
+    e = np.unique(e, axis=0)
+    g = W.from_edges(n, e, rng.uniform(0.5, 2.0, size=e.shape[0]))
+    per_tile = np.diff(g.row_ptr[::32])
+    assert per_tile.max() > 4096 and per_tile.min() <= 4096
+    w64 = g.w.astype(np.float64)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w64)
+    s = oracle.strength(g.n, g.row_ptr, g.col_idx, w64)
+    lmax = oracle.lmax_estimate(L, s, W.start_vector(g.n, 3), 60)
+    p = 12
+    a = oracle.cheb_coeffs(0.1 * lmax, lmax, p)
+    Rs, R64 = W.signals(g.n, r, 22)
+    G64 = W.signals_f64(g.n, r, 23).astype(np.float32).astype(np.float64)
+    Gd = upload_graph(g)
+    Rd = block_f32(Rs)
+    Y, ck = asc.cheb_filter(Gd, scalar(lmax), to_dev(a), Rd, ckpt_stride=c)
+    dW, dc = asc.cheb_filter_bwd(Gd, scalar(lmax), to_dev(a), Rd, ck, c, block_f32(G64))
+    dw_ref, da_ref = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w64, lmax, a, R64, G64)
+    assert rel_fro(host(dW), dw_ref) <= TOL_DW
+    assert rel_fro(host(dc), da_ref) <= TOL_DA
