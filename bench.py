@@ -130,6 +130,15 @@ def _time(fn, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
+def planted_ari(labels_dev, planted):
+    """Adjusted Rand index of the clustering against the generator's planted
+    blocks (scikit-learn; a quality figure of the run, not a parity check)."""
+    if planted is None:
+        return None
+    from sklearn.metrics import adjusted_rand_score
+    return round(float(adjusted_rand_score(planted, labels_dev.cpu().numpy())), 4)
+
+
 def _progress(msg):
     """One line per finished phase on stderr (the JSON line stays alone on stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -412,7 +421,7 @@ def extra_mid(dev):
         for _ in range(cfg["kmeans_iters"]):
             lab, _ = asc.kmeans_assign(Y, C)
             asc.kmeans_update(Y, lab, C)
-        asc.kmeans_assign(Y, C)
+        pipeline.labels = asc.kmeans_assign(Y, C)[0]
         m[4].record()
         return m
 
@@ -423,6 +432,7 @@ def extra_mid(dev):
     parts = ["lambda_k_filter", "normalize", "kmeanspp", "kmeans"]
     pipe = {nm: round(float(np.mean([m[q].elapsed_time(m[q + 1]) for m in runs])), 3) for q, nm in enumerate(parts)}
     pipe["total"] = round(float(np.mean([m[0].elapsed_time(m[4]) for m in runs])), 3)
+    pipe["ari_vs_planted"] = planted_ari(pipeline.labels, g.labels)
     del states
     return {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ms_per_filter_fwd": round(ms, 3),
             "pipeline_ms": pipe,
@@ -643,6 +653,7 @@ def main():
     ms_step = wall * 1e3 / args.steps
     lmax_h = float(out[0].cpu()[0])
     lam_k_h = float(out[1].cpu()[0])
+    ari_planted = planted_ari(out[2], g.labels)
 
     # filter alone (fp32 and bf16), events on the launch stream
     # 3 warm-up filters, then 20 back-to-back filters with an event between
@@ -910,6 +921,7 @@ def main():
         "kmeanspp_ms": round(ms_kpp, 3),
         "lambda_max": lmax_h,
         "lambda_k_est": lam_k_h,
+        "ari_vs_planted": ari_planted,
         "pattern_only": None if ms_pat is None else {
             "ms_per_filter_fwd": round(ms_pat, 4), "gbs": round(p * bs_pat / (ms_pat * 1e-3) / 1e9, 2)},
         "roofline": {"bound": "hbm", "achieved": round(alg_launch / (launch_ms * 1e-3) / 1e9, 2),

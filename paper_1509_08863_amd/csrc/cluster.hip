@@ -324,27 +324,11 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
 #pragma unroll
         for (int t = 0; t < NTILE; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
         double nf = 0.0;
-        // four column steps per pass; the row values of the next pass are
-        // loaded while this pass's products run (the products and sums still
-        // run step by step, in column order)
-        float bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int col = 4 * u + lk;
-            bv[u] = (live && col < r) ? fr[col] : 0.0f;
-        }
-        for (int st0 = 0; st0 < steps; st0 += 4) {
-            float bn[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int col = 4 * (st0 + 4 + u) + lk;
-                bn[u] = (live && col < r) ? fr[col] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (st0 + u >= steps) break;
-                const int col = 4 * (st0 + u) + lk;
-                const float b = bv[u];
+        if constexpr (kStageRows) {
+            // rows in LDS: one column step at a time
+            for (int st = 0; st < steps; ++st) {
+                const int col = 4 * st + lk;
+                const float b = (live && col < r) ? fr[col] : 0.0f;
                 nf += (double)b * (double)b;
 #pragma unroll
                 for (int t = 0; t < NTILE; ++t) {
@@ -352,8 +336,43 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
                 }
             }
+        } else {
+            // rows read from global memory: four column steps per pass, the
+            // row values of the next pass loaded while this pass's products
+            // run (products and sums still step by step, in column order;
+            // clamped in-range addresses, always issued)
+            float bv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bv[u] = bn[u];
+            for (int u = 0; u < 4; ++u) {
+                const int col = 4 * u + lk;
+                const bool in = live && col < r;
+                const float x = fr[in ? col : 0];
+                bv[u] = in ? x : 0.0f;
+            }
+            for (int st0 = 0; st0 < steps; st0 += 4) {
+                float bn[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = 4 * (st0 + 4 + u) + lk;
+                    const bool in = live && col < r;
+                    const float x = fr[in ? col : 0];
+                    bn[u] = in ? x : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (st0 + u >= steps) break;
+                    const int col = 4 * (st0 + u) + lk;
+                    const float b = bv[u];
+                    nf += (double)b * (double)b;
+#pragma unroll
+                    for (int t = 0; t < NTILE; ++t) {
+                        const float a = Cs[(16 * t + li) * RP + col];
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) bv[u] = bn[u];
+            }
         }
         // |f|^2 of row li: the four lanes li, li+16, li+32, li+48 hold its columns
         nf += __shfl_xor(nf, 16, 64);
@@ -411,17 +430,20 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
                 const int c = 16 * (slot >> 2) + 4 * lk + (slot & 3);
                 const float *cr = Cs + c * RP;
                 double d = 0.0;
-                // eight row values loaded per pass, then summed in column order
+                // rows in global memory: eight row values loaded per pass, then
+                // summed in column order
                 int64_t col = 0;
-                for (; col + 8 <= r; col += 8) {
-                    float fv[8];
+                if constexpr (!kStageRows) {
+                    for (; col + 8 <= r; col += 8) {
+                        float fv[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) fv[q] = fr[col + q];
+                        for (int q = 0; q < 8; ++q) fv[q] = fr[col + q];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const double diff = (double)fv[q] - (double)cr[col + q];
-                        const double sq = diff * diff;
-                        d = d + sq;
+                        for (int q = 0; q < 8; ++q) {
+                            const double diff = (double)fv[q] - (double)cr[col + q];
+                            const double sq = diff * diff;
+                            d = d + sq;
+                        }
                     }
                 }
                 for (; col < r; ++col) {
@@ -539,15 +561,25 @@ __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, in
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t i1 = min(n, i0 + rows_per_block);
-    constexpr int U = 8;
+    // 16 rows' labels and values loaded before they are added (clamped
+    // in-range addresses, always issued: no load waits behind a branch)
+    constexpr int U = 16;
     for (int64_t ib = i0; ib < i1; ib += U) {
         int lab[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
+        for (int u = 0; u < U; ++u) {
+            const bool in = ib + u < i1;
+            const int l = labels[in ? ib + u : i1 - 1];
+            lab[u] = in ? l : -1;
+        }
         for (int64_t col = threadIdx.x; col < r; col += blockDim.x) {
             float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (ib + u < i1) ? F[(ib + u) * ldf + col] : 0.0f;
+            for (int u = 0; u < U; ++u) {
+                const bool in = ib + u < i1;
+                const float x = F[(in ? ib + u : i1 - 1) * ldf + col];
+                v[u] = in ? x : 0.0f;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = lab[u];
@@ -590,15 +622,25 @@ __global__ __launch_bounds__(256) void update_partial4_kernel(const float *__res
     const int64_t q4 = (len + 3) / 4;
     const int64_t i0 = min(b1, b0 + wave * q4);
     const int64_t i1 = min(b1, i0 + q4);
+    // 8 rows' labels and values loaded before they are added (clamped
+    // in-range addresses, always issued: no load waits behind a branch)
     constexpr int U = 8;
     for (int64_t ib = i0; ib < i1; ib += U) {
         int lab[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
+        for (int u = 0; u < U; ++u) {
+            const bool in = ib + u < i1;
+            const int l = labels[in ? ib + u : i1 - 1];
+            lab[u] = in ? l : -1;
+        }
         for (int64_t col = lane; col < r; col += 64) {
             float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (ib + u < i1) ? F[(ib + u) * ldf + col] : 0.0f;
+            for (int u = 0; u < U; ++u) {
+                const bool in = ib + u < i1;
+                const float x = F[(in ? ib + u : i1 - 1) * ldf + col];
+                v[u] = in ? x : 0.0f;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = lab[u];
@@ -650,14 +692,22 @@ __global__ __launch_bounds__(256) void update_slots_kernel(const float *__restri
     const int64_t q = (len + ncopy - 1) / ncopy;
     const int64_t i0 = min(b1, b0 + id * q);
     const int64_t i1 = min(b1, i0 + q);
+    // 8 rows' labels and values are loaded before they are added (rows still
+    // added one by one, in order).  The loads use clamped in-range addresses
+    // and are always issued, so none of them waits behind a branch.
     constexpr int U = 8;
+    const int colc = col < r ? col : (int)r - 1;
     for (int64_t ib = i0; ib < i1; ib += U) {
         int lab[U];
         float v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            lab[u] = (ib + u < i1) ? labels[ib + u] : -1;
-            v[u] = (ib + u < i1 && col < r) ? F[(ib + u) * ldf + col] : 0.0f;
+            const bool in = ib + u < i1;
+            const int64_t i = in ? ib + u : i1 - 1;
+            const int l = labels[i];
+            const float x = F[i * ldf + colc];
+            lab[u] = in ? l : -1;
+            v[u] = (in && col < r) ? x : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
