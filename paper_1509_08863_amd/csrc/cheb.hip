@@ -758,6 +758,36 @@ asc_status run_store(const asc_graph *g, const double *lmax, int p, const void *
     const size_t pbytes = panel_bytes(n, P.rs, sig);
     auto slot = [&](int sl, int j) -> void * { return static_cast<char *>(states) + ((size_t)sl * (p + 1) + j) * pbytes; };
     const int64_t pstride = (int64_t)((size_t)(p + 1) * pbytes / esize(sig));
+    // Small graphs: every slice in one launch per step (blockIdx.y = slice),
+    // instead of one launch per slice and step, while all the slices' panels
+    // stay a cache-resident set (the launches, not the memory, bound these).
+    if (P.np == 1 && P.nslices > 1 && P.nslices <= 65535 && (size_t)P.nslices * pbytes <= (size_t(64) << 20)) {
+        Plan Py = P;
+        Py.var &= ~4u;  // the XCD-band tile order assumes a one-dimensional grid
+        for (int sl = 0; sl < P.nslices; ++sl) {
+            pack_panels(Py, n, R, sig, ldr, r, sl, slot(sl, 0), pstride, s);
+            ASC_LAUNCHED();
+        }
+        StepArgs A{};
+        A.pstride = pstride;
+        A.ystride = (int64_t)((size_t)(p + 1) * pbytes);
+        A.n = n;
+        A.rp = g->row_ptr;
+        A.ci = g->col_idx;
+        A.w = g->w;
+        A.diag = F.diag;
+        A.beta = F.beta;
+        const dim3 gy((unsigned)grid, (unsigned)P.nslices);
+        for (int j = 0; j < p; ++j) {
+            A.cur = slot(0, j);
+            A.prev = j == 0 ? nullptr : slot(0, j - 1);
+            A.out = slot(0, j + 1);
+            A.j = j;
+            hipError_t e = launch_step(sig, Py.lpr, Py.var, j == 0 ? M_FIRST : 0u, A, gy, s);
+            if (e != hipSuccess) return fail(ASC_ERR_HIP, "cheb_step launch failed: %s", hipGetErrorString(e));
+        }
+        return ASC_OK;
+    }
     for (int sl = 0; sl < P.nslices; sl += P.np) {
         pack_panels(P, n, R, sig, ldr, r, sl, slot(sl, 0), pstride, s);
         ASC_LAUNCHED();

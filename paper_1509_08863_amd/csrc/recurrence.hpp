@@ -114,6 +114,8 @@ struct StepArgs {
     void *ck_b;            // if set: T_{j+1} checkpoint block
     int64_t ck_ld;
     int64_t pstride;       // NP > 1: elements from one slice's panel to the next one's
+    int64_t ystride;       // gridDim.y > 1 (state-store passes of small graphs): bytes from one
+                           // slice's panels (cur, prev, out) to the next slice's; no Y, no partials
 };
 
 // The rest of a row's step for one panel: T_{j+1} from the gathered sum, its
@@ -324,6 +326,13 @@ __device__ __forceinline__ void step_row(const StepArgs &A, const int64_t row, c
 
 template <typename TS, int LPR, unsigned MODE, unsigned VAR, int NP = 1>
 __global__ __launch_bounds__(NT) void cheb_step(StepArgs A) {
+    if (gridDim.y > 1) {
+        // one slice per blockIdx.y: its own panels, A.ystride bytes apart
+        const int64_t off = (int64_t)blockIdx.y * A.ystride;
+        A.cur = static_cast<const char *>(A.cur) + off;
+        A.prev = A.prev ? static_cast<const char *>(A.prev) + off : nullptr;
+        A.out = static_cast<char *>(A.out) + off;
+    }
     constexpr int RPW = 64 / LPR;
     constexpr int ROWS = RPW * (NT / 64);
     const int lane = threadIdx.x & 63;
@@ -539,7 +548,7 @@ int grid_for(int64_t n, int lpr) {
 }
 
 template <typename TS, int LPR, unsigned VAR, int NP = 1>
-hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t s) {
+hipError_t launch_step_v(unsigned mode, const StepArgs &A, dim3 grid, hipStream_t s) {
     switch (mode) {
         case 0: cheb_step<TS, LPR, 0, VAR, NP><<<grid, NT, 0, s>>>(A); break;
         case 1: cheb_step<TS, LPR, 1, VAR, NP><<<grid, NT, 0, s>>>(A); break;
@@ -557,7 +566,7 @@ hipError_t launch_step_v(unsigned mode, const StepArgs &A, int grid, hipStream_t
 }
 
 template <typename TS, int LPR>
-hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int grid, hipStream_t s) {
+hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, dim3 grid, hipStream_t s) {
     switch (var & 7u) {
         case 1u: return launch_step_v<TS, LPR, 1u>(mode, A, grid, s);
         case 2u: return launch_step_v<TS, LPR, 2u>(mode, A, grid, s);
@@ -570,7 +579,7 @@ hipError_t launch_step_t(unsigned mode, unsigned var, const StepArgs &A, int gri
     }
 }
 
-hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const StepArgs &A, int grid,
+hipError_t launch_step(asc_dtype dt, int lpr, unsigned var, unsigned mode, const StepArgs &A, dim3 grid,
                        hipStream_t s) {
     if (dt == ASC_F32) {
         switch (lpr) {

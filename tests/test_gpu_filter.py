@@ -262,3 +262,25 @@ def test_lmax_column_blocked_products_match_oracle(n, blocks, weighted):
     ref = oracle.lmax_estimate(L, s, v0, 30)
     _, got = asc.lmax_estimate(G, to_dev(v0), 30, host=True)
     assert got == pytest.approx(ref, rel=1e-9)
+
+
+@pytest.mark.parametrize("var", [0, 4])
+def test_filter_on_block_ordered_graph(var):
+    # the same SBM with every generating block contiguous: the filter of the
+    # relabelled graph on the relabelled signals is the relabelled filter
+    # (each against the float64 oracle of its own graph), on both tile orders
+    g = W.sbm(W.dirichlet_sizes(30000, 12, 5.0, 31), 16.0, 0.05, 32)
+    h, perm = W.block_order(g)
+    r, p = 40, 40
+    Rs, R64 = W.signals(g.n, r, 33)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+    s = oracle.strength(g.n, g.row_ptr, g.col_idx, None)
+    lmax = oracle.lmax_estimate(L, s, W.start_vector(g.n, 34), 40)
+    a = oracle.cheb_coeffs(0.15 * lmax, lmax, p)
+    Yo = oracle.cheb_filter(L, lmax, a, R64)
+    for graph, R_, ref in ((g, Rs, Yo), (h, Rs[perm], Yo[perm])):
+        Gd = upload_graph(graph)
+        asc.tune_set(Gd, r, torch.float32, 32, var)
+        Y = host(asc.cheb_filter(Gd, scalar(lmax), to_dev(a), block_f32(R_)))
+        asc.tune_set(Gd, r, torch.float32, 0, 0)
+        assert rel_fro(Y, ref) <= 1e-5
