@@ -41,12 +41,12 @@ HBM_PEAK_GBS = 8000.0
 # variant; valid only while the kernel source is the one measured (sha1 of the
 # step-kernel region of recurrence.hpp), otherwise reported null.
 STEP_TRAFFIC = {
-    "src_sha1": "7770077e6e0e8b5618d05ee3d3db1d4c8837c990",
+    "src_sha1": "fe387ae335732b0e00bdf449e9fa3432ce6662d3",
     "workload": "sbm_n1e6_k50dir_d30_r96_p150",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # (slice_cols, variant) -> (FETCH_SIZE, WRITE_SIZE) in KiB, average over the
     # 2700 step launches of 6 filters (steps that update Y and steps that do not)
-    "kib_per_launch": {(32, 4): (2192482.04, 188338.45), (32, 0): (2202944.85, 188338.45)},
+    "kib_per_launch": {(32, 4): (2192537.93, 188338.45)},
 }
 
 
@@ -61,13 +61,13 @@ ADJ_TRAFFIC = {
 }
 
 # The recurrence step on the same graph with each generating block's nodes
-# contiguous (block order, round-robin tiles): average over the 2664 step
+# contiguous (block order, round-robin tiles): average over the 2700 step
 # launches of 6 filters (steps with and without Y).
 BLOCK_STEP_TRAFFIC = {
-    "src_sha1": "7770077e6e0e8b5618d05ee3d3db1d4c8837c990",
+    "src_sha1": "fe387ae335732b0e00bdf449e9fa3432ce6662d3",
     "workload": "sbm_n1e6_k50dir_d30_r96_p150",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "kib_per_launch": {(32, 0): (2142150.7, 187500.0)},
+    "kib_per_launch": {(32, 0): (2143150.71, 188338.45)},
 }
 
 
