@@ -961,7 +961,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "node_order": args.order, "n": n, "nnz": nnz, "r": r, "p": p, "k": k,
+        "config": {"workload": cfg["name"], "node_order": args.order, "seeds": seeds, "n": n, "nnz": nnz, "r": r,
+                   "p": p, "k": k,
                    "dichotomy_steps": steps_dich, "kmeans_iters": km_iters},
         "ms_per_filter_fwd": round(ms_f32, 4),
         "ms_per_filter_fwd_stats": stats_f32,
@@ -1007,6 +1008,7 @@ def main():
                              for f in health.values())},
         "extra": extra,
         "gen_s": round(gen_s, 1),
+        "software": {"hip": torch.version.hip, "torch": torch.__version__, "device": torch.cuda.get_device_name(0)},
     }
     print(json.dumps(line))
     if not line["health"]["ok"]:

@@ -10,7 +10,18 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cpu_baseline.c")
-LIB = os.path.join(HERE, "_cpu_baseline.so")
+# ORACLE_CPU_BASELINE_LIB names another build of the same source (the
+# sanitizer build of the host checks); by default the in-tree library
+LIB = os.environ.get("ORACLE_CPU_BASELINE_LIB") or os.path.join(HERE, "_cpu_baseline.so")
+
+
+def build_sanitized(out_path: str) -> str:
+    """The same source under AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc), for the host sanitizer test; loading it needs libasan preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fopenmp", "-fPIC", "-shared", "-std=c99", SRC, "-o", out_path]
+    subprocess.check_call(cmd)
+    return out_path
 
 
 def build() -> str:

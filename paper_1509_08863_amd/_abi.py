@@ -124,6 +124,13 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        # ASC_TUNE_CACHE: a tuning table saved by asc_tune_save, loaded once here
+        # (the library itself reads no environment)
+        cache = os.environ.get("ASC_TUNE_CACHE")
+        if cache and os.path.exists(cache):
+            st = L.asc_tune_load(cache.encode())
+            if st != ASC_OK:
+                raise AscError(st, f"ASC_TUNE_CACHE={cache}: " + L.asc_last_error().decode(errors="replace"))
         _lib = L
     return _lib
 

@@ -249,3 +249,19 @@ def test_noalloc_filter_rejects_beyond_its_scratch_before_any_device_call():
     g0 = _g(10, 0)
     assert L.asc_cheb_filter_noalloc(ctypes.byref(g0), fake, fake, -1, fake, 0, 8, 8, fake, 8, None, 0,
                                      None) == _abi.ASC_ERR_INVALID
+
+
+def test_tune_cache_environment_is_loaded_at_first_use(tmp_path):
+    # a child process with ASC_TUNE_CACHE set sees the saved entry on first use
+    import subprocess
+    import sys
+    path = tmp_path / "tune.json"
+    path.write_text('[\n{"n": 777, "nnz": 5, "r": 24, "dtype": 0, "slice_cols": 8, "variant": 3, "ms": 0.1}\n]\n')
+    code = ("import ctypes; from paper_1509_08863_amd import _abi; L = _abi.lib(); "
+            "a, b = ctypes.c_int(0), ctypes.c_int(0); "
+            "assert L.asc_tune_get(777, 5, 24, 0, ctypes.byref(a), ctypes.byref(b)) == 0; print(a.value, b.value)")
+    env = dict(os.environ, ASC_TUNE_CACHE=str(path))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split() == ["8", "3"]

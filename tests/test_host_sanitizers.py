@@ -67,3 +67,50 @@ def test_sanitized_library_is_instrumented_and_loaded(sanitized_lib):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == lib
+
+
+def _gcc_asan_runtime():
+    r = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    return path if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path) else None
+
+
+def test_cpu_baseline_clean_under_asan_and_ubsan(tmp_path):
+    # the plain-C float64 recurrence (the CPU baseline the bench times) built
+    # with gcc's sanitizers, run on a small weighted graph with an isolated
+    # node against the NumPy oracle, in a child process with libasan preloaded
+    import oracle.cpu_baseline as cb
+    rt = _gcc_asan_runtime()
+    if rt is None:
+        pytest.skip("no gcc ASan runtime")
+    lib = cb.build_sanitized(str(tmp_path / "cpu_baseline_sanitize.so"))
+    env = dict(os.environ)
+    env["ORACLE_CPU_BASELINE_LIB"] = lib
+    env["LD_PRELOAD"] = rt + ((" " + env["LD_PRELOAD"]) if env.get("LD_PRELOAD") else "")
+    env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["OMP_NUM_THREADS"] = "4"
+    code = """
+import numpy as np, oracle, workloads as W
+import oracle.cpu_baseline as cb
+assert cb.LIB.endswith('cpu_baseline_sanitize.so')
+g = W.random_weighted(300, 0.05, 3, isolated=1)
+w = g.w.astype(np.float64)
+L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w)
+lm = oracle.lmax_estimate(L, oracle.strength(g.n, g.row_ptr, g.col_idx, w), W.start_vector(g.n, 5), 60)
+R = W.signals_f64(g.n, 7, 4)
+for p in (0, 1, 2, 25):
+    a = oracle.cheb_coeffs(0.2 * lm, lm, p)
+    Y = cb.cheb_filter(g.n, g.row_ptr, g.col_idx, w, lm, a, R)
+    Yo = oracle.cheb_filter(L, lm, a, R)
+    assert np.max(np.abs(Y - Yo)) <= 1e-12 * max(1.0, np.max(np.abs(Yo))), p
+mu = cb.cheb_moments(g.n, g.row_ptr, g.col_idx, w, lm, 25, R)
+mu_o = oracle.moments(L, lm, 25, R)
+assert np.max(np.abs(mu - mu_o)) <= 1e-10 * abs(mu_o[0])
+print('sanitized baseline ok')
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT, timeout=300)
+    out = r.stdout + r.stderr
+    assert "AddressSanitizer" not in out and "runtime error:" not in out, out[-4000:]
+    assert r.returncode == 0, out[-4000:]
+    assert "sanitized baseline ok" in out
