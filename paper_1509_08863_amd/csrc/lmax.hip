@@ -156,8 +156,10 @@ __global__ void lz_split_kernel(int64_t n, const int32_t *__restrict__ rp, const
 
 // pass b of w = L v_j - beta_j v_{j-1}: the segment sums of column range b
 // are added to the running row sums in w; the last pass forms w and the
-// partial <w, v_j> as lz_spmv_kernel does
-template <bool LAST>
+// partial <w, v_j> as lz_spmv_kernel does.  Unit weights (w = NULL) and
+// stored weights are separate instantiations, so a lane's index and weight
+// loads go out together instead of the weight load waiting behind a branch.
+template <bool LAST, bool WEIGHTED>
 __global__ void lz_spmv_block_kernel(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                      const float *__restrict__ wgt, const int32_t *__restrict__ off, int B, int b,
                                      const double *__restrict__ s, const double *__restrict__ v,
@@ -176,7 +178,7 @@ __global__ void lz_spmv_block_kernel(int64_t n, const int32_t *__restrict__ rp, 
         if (i < n) {
             const int32_t e0 = b == 0 ? rp[i] : off[(int64_t)(b - 1) * n + i];
             const int32_t e1 = b == B - 1 ? rp[i + 1] : off[(int64_t)b * n + i];
-            for (int32_t e = e0 + t; e < e1; e += LPR) sum += (wgt ? (double)wgt[e] : 1.0) * v[ci[e]];
+            for (int32_t e = e0 + t; e < e1; e += LPR) sum += (WEIGHTED ? (double)wgt[e] : 1.0) * v[ci[e]];
         }
         sum += __shfl_xor(sum, 1, 64);
         sum += __shfl_xor(sum, 2, 64);
@@ -343,11 +345,30 @@ extern "C" asc_status asc_lmax_estimate(const asc_graph *g, const double *v0, in
             lz_spmv_kernel<<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, g->strength, vcur, vprev, wv, beta, j,
                                               st, part);
         } else {
-            for (int b = 0; b < B - 1; ++b)
-                lz_spmv_block_kernel<false><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off, B, b,
-                                                               g->strength, vcur, vprev, wv, beta, j, st, part);
-            lz_spmv_block_kernel<true><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off, B, B - 1,
-                                                          g->strength, vcur, vprev, wv, beta, j, st, part);
+            // unit weights (w = NULL) and stored weights take separate
+            // kernels, so no weight load sits behind a branch
+            for (int b = 0; b < B; ++b) {
+                const bool last = b == B - 1;
+                if (g->w) {
+                    if (last)
+                        lz_spmv_block_kernel<true, true><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off, B,
+                                                                            b, g->strength, vcur, vprev, wv, beta, j,
+                                                                            st, part);
+                    else
+                        lz_spmv_block_kernel<false, true><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off, B,
+                                                                             b, g->strength, vcur, vprev, wv, beta, j,
+                                                                             st, part);
+                } else {
+                    if (last)
+                        lz_spmv_block_kernel<true, false><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off,
+                                                                             B, b, g->strength, vcur, vprev, wv, beta,
+                                                                             j, st, part);
+                    else
+                        lz_spmv_block_kernel<false, false><<<nbs, NT, 0, s>>>(n, g->row_ptr, g->col_idx, g->w, off,
+                                                                              B, b, g->strength, vcur, vprev, wv,
+                                                                              beta, j, st, part);
+                }
+            }
         }
         ASC_LAUNCHED();
         lz_axpy_kernel<<<nb, NT, 0, s>>>(n, nbs, part, wv, vcur, u, alpha, j, st, partmax);
