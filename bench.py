@@ -419,9 +419,9 @@ def extra_mid(dev):
         C = asc.kmeans_init_rows(Y, asc.kmeans_pp(Y, k, U))
         m[3].record()
         for _ in range(cfg["kmeans_iters"]):
-            lab, _ = asc.kmeans_assign(Y, C)
+            lab, _ = asc.kmeans_assign(Y, C, dist=False)
             asc.kmeans_update(Y, lab, C)
-        pipeline.labels = asc.kmeans_assign(Y, C)[0]
+        pipeline.labels = asc.kmeans_assign(Y, C, dist=False)[0]
         m[4].record()
         return m
 
@@ -442,9 +442,9 @@ def extra_mid(dev):
         asc.normalize_features(Y, want_norms=False)
         C = asc.kmeans_init_rows(Y, asc.kmeans_pp(Y, k, U))
         for _ in range(cfg["kmeans_iters"]):
-            lab, _ = asc.kmeans_assign(Y, C)
+            lab, _ = asc.kmeans_assign(Y, C, dist=False)
             asc.kmeans_update(Y, lab, C)
-        return asc.kmeans_assign(Y, C)[0]
+        return asc.kmeans_assign(Y, C, dist=False)[0]
 
     pipeline_n()
     ms_n = _time(pipeline_n, 5)
@@ -644,9 +644,9 @@ def main():
         marks[6].record()
         C = asc.kmeans_init_rows(Y, initd)
         for _ in range(km_iters):
-            lab, _ = asc.kmeans_assign(Y, C)
+            lab, _ = asc.kmeans_assign(Y, C, dist=False)
             asc.kmeans_update(Y, lab, C)
-        lab, _ = asc.kmeans_assign(Y, C)
+        lab, _ = asc.kmeans_assign(Y, C, dist=False)
         marks[7].record()
         if rec is not None:
             rec.append(marks)
@@ -712,9 +712,9 @@ def main():
             asc.normalize_features(Y, want_norms=False)
             C = asc.kmeans_init_rows(Y, asc.kmeans_pp(Y, k, Ukpp))
             for _ in range(km_iters):
-                lab_n, _ = asc.kmeans_assign(Y, C)
+                lab_n, _ = asc.kmeans_assign(Y, C, dist=False)
                 asc.kmeans_update(Y, lab_n, C)
-            lab_n, _ = asc.kmeans_assign(Y, C)
+            lab_n, _ = asc.kmeans_assign(Y, C, dist=False)
             return lam_n, lab_n
 
         step_norm()

@@ -223,7 +223,8 @@ asc_status asc_normalize_features(float *Y, int64_t n, int64_t r, int64_t ldy, f
  *   r <= 4096.  For 2 <= k <= 64 (and r small enough for LDS) the candidates
  *   come from float32 matrix-core distances with a rigorous error bound and
  *   only the centroids that could be nearest are evaluated by the float64
- *   definition; the results are the definition's either way.
+ *   definition (with dist2 NULL, not even the winner when it is the only
+ *   such centroid); the results are the definition's either way.
  * update: C[c] = mean of the members of c (float64 sums in a fixed order,
  *   rounded to float32); an empty cluster keeps its previous centroid;
  *   counts[k] (int64, may be NULL) gets the member counts.

@@ -271,11 +271,13 @@ def kmeans_init_rows(F: torch.Tensor, rows: torch.Tensor) -> torch.Tensor:
     return C
 
 
-def kmeans_assign(F: torch.Tensor, C: torch.Tensor):
+def kmeans_assign(F: torch.Tensor, C: torch.Tensor, dist: bool = True):
+    """(labels, dist2); dist=False returns (labels, None) and lets the library
+    skip the float64 distance of rows whose nearest centroid is already certain."""
     n, r = F.shape
     k = C.shape[0]
     labels = torch.empty(n, dtype=torch.int32, device=F.device)
-    dist2 = torch.empty(n, dtype=torch.float32, device=F.device)
+    dist2 = torch.empty(n, dtype=torch.float32, device=F.device) if dist else None
     _abi.check(_abi.lib().asc_kmeans_assign(_ptr(F), n, r, _ld(F), _ptr(C.contiguous()), k, _ptr(labels),
                                             _ptr(dist2), _stream()))
     return labels, dist2

@@ -419,6 +419,17 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
                 if (all || lb <= bub) need |= 1u << (4 * t + v);
             }
         if (!live) need = 0;
+        // A lone candidate is the float32 winner, and the float64 winner for
+        // certain: every other centroid lies beyond the winner's upper bound.
+        // Its float64 distance is then only needed as an output.
+        bool sure = false;
+        if (!dist2 && !dist64) {
+            int cnt = __popc(need);
+            cnt += __shfl_xor(cnt, 16, 64);
+            cnt += __shfl_xor(cnt, 32, 64);
+            sure = cnt == 1;
+            if (sure) need = 0;
+        }
         // one pass of the column loop per needed centroid of the busiest lane
         // (usually one: the winner's own lane)
         double ed = __builtin_huge_val();
@@ -468,6 +479,7 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
                 ec = oc;
             }
         }
+        if (sure) ec = bc;
         if (live && lk == 0) {
             labels[row] = ec;
             if (dist2) dist2[row] = (float)ed;

@@ -110,6 +110,11 @@ def test_kmeans_assign_bit_exact(n, r, k):
     lab_ref, d_ref = oracle.kmeans_assign(F, C)
     np.testing.assert_array_equal(host(labels), lab_ref)
     np.testing.assert_array_equal(host(dist2), d_ref.astype(np.float32))
+    # without the distance output (the float64 distance is skipped where the
+    # candidate is certain): the same labels
+    labels_nd, none = asc.kmeans_assign(block_f32(F), to_dev(C), dist=False)
+    assert none is None
+    np.testing.assert_array_equal(host(labels_nd), lab_ref)
 
 
 @pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (20000, 96, 50), (100, 8, 7)])
@@ -178,3 +183,5 @@ def test_kmeans_assign_near_ties_stay_exact(n, r, k):
     lab_ref, d_ref = oracle.kmeans_assign(F[ok], C)
     np.testing.assert_array_equal(host(labels)[ok], lab_ref)
     np.testing.assert_array_equal(host(dist2)[ok], d_ref.astype(np.float32))
+    labels_nd, _ = asc.kmeans_assign(block_f32(F), to_dev(C), dist=False)
+    np.testing.assert_array_equal(host(labels_nd), host(labels))
