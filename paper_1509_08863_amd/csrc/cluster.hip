@@ -21,8 +21,7 @@ struct Bat {
     int64_t l;       // elements between label / distance blocks
     int64_t rows;    // elements between init-row blocks
 };
-constexpr Bat kOne{0, 1, 0, 0, 0};
-__device__ __forceinline__ int64_t fblk(const Bat &b) { return (int64_t)(blockIdx.y / b.fdiv) * b.f; }
+__device__ __forceinline__ int64_t fblk(const Bat &b, unsigned y) { return (int64_t)(y / b.fdiv) * b.f; }
 
 // one wavefront per row: |y_i| accumulated in float64, y_i /= |y_i|
 __global__ __launch_bounds__(NT) void normalize_kernel(float *__restrict__ Y, int64_t n, int64_t r, int64_t ldy,
@@ -48,7 +47,7 @@ __global__ __launch_bounds__(NT) void normalize_kernel(float *__restrict__ Y, in
 
 __global__ void init_rows_kernel(const float *__restrict__ F, int64_t n, int64_t r, int64_t ldf,
                                  const int32_t *__restrict__ rows, int k, float *__restrict__ C, Bat bt) {
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     rows += blockIdx.y * bt.rows;
     C += blockIdx.y * bt.c;
     const int64_t total = (int64_t)k * r;
@@ -79,7 +78,7 @@ __global__ __launch_bounds__(NT) void assign_kernel(const float *__restrict__ F,
                                                     double *__restrict__ dist64, Bat bt) {
 #pragma clang fp contract(off)
     extern __shared__ float Ct[];
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     Cg += blockIdx.y * bt.c;
     labels += blockIdx.y * bt.l;
     if (dist2) dist2 += blockIdx.y * bt.l;
@@ -155,7 +154,7 @@ __global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict
                                                          double *__restrict__ dist64, Bat bt) {
 #pragma clang fp contract(off)
     extern __shared__ double Cd[];
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     Cg += blockIdx.y * bt.c;
     labels += blockIdx.y * bt.l;
     if (dist2) dist2 += blockIdx.y * bt.l;
@@ -261,7 +260,7 @@ __global__ __launch_bounds__(NT) void assign_rows_kernel(const float *__restrict
 // row's result: the others cannot be nearer.  Labels and distances therefore
 // equal the definition's.  A row with non-finite values evaluates every
 // centroid.
-template <int NTILE>
+template <int NTILE, bool STAGE>
 __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict__ F, int64_t n, int64_t r,
                                                          int64_t ldf, const float *__restrict__ Cg, int k,
                                                          int32_t *__restrict__ labels, float *__restrict__ dist2,
@@ -274,9 +273,9 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     double *cn = lds_d;                                   // |c|^2, KC values
     double *cs = lds_d + KC;                              // |c|, KC values
     float *Cs = reinterpret_cast<float *>(lds_d + 2 * KC);  // [KC][RP], zero-padded
-    constexpr bool kStageRows = NTILE <= 2;
+    constexpr bool kStageRows = STAGE;
     float *Fs = Cs + KC * RP + (threadIdx.x >> 6) * 16 * RP;  // this wavefront's rows (staged only)
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     Cg += blockIdx.y * bt.c;
     labels += blockIdx.y * bt.l;
     if (dist2) dist2 += blockIdx.y * bt.l;
@@ -300,6 +299,11 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     const int li = lane & 15, lk = lane >> 4;
     const int steps = (int)((r + 3) >> 2);
     const double ecoef = 3.0 * (double)(r + 2) * 0x1p-24;
+    // staged rows: element q = rl * RP + col of the wavefront's 16 LDS rows;
+    // lane q0 + lane starts at (rl0, col0), and each further load is 64
+    // elements on, (d64, m64) rows and columns (no division per element)
+    const int rl0 = lane / RP, col0 = lane - rl0 * RP;
+    const int d64 = 64 / RP, m64 = 64 - d64 * RP;
     const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
     for (int64_t g = wave0; g * 16 < n; g += nwaves) {
@@ -310,10 +314,30 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
         // hide the loads behind); above, each lane reads its row from F
         const float *fr;
         if constexpr (kStageRows) {
-            for (int q = lane; q < 16 * RP; q += 64) {
-                const int rl = q / RP, col = q - rl * RP;
-                const int64_t rr = g * 16 + rl;
-                Fs[q] = (rr < n && col < r) ? F[rr * ldf + col] : 0.0f;
+            // four loads in flight per lane, from clamped in-range addresses and
+            // always issued, then their LDS stores; zero past r and past n
+            const int64_t left = n - g * 16;  // rows of this group that exist (>= 1)
+            const float *fg = F + g * 16 * ldf;
+            int rl = rl0, col = col0;
+            for (int q0 = 0; q0 < 16 * RP; q0 += 4 * 64) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = rl < 16 && rl < left && col < r;
+                    const float x = fg[in ? (int64_t)rl * ldf + col : 0];
+                    v[u] = in ? x : 0.0f;
+                    rl += d64;
+                    col += m64;
+                    if (col >= RP) {
+                        col -= RP;
+                        ++rl;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * 64 + lane;
+                    if (q < 16 * RP) Fs[q] = v[u];
+                }
             }
             __builtin_amdgcn_wave_barrier();
             fr = Fs + li * RP;
@@ -325,10 +349,29 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
         for (int t = 0; t < NTILE; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
         double nf = 0.0;
         if constexpr (kStageRows) {
-            // rows in LDS: one column step at a time
-            for (int st = 0; st < steps; ++st) {
+            // rows in LDS (zero past r and past n): the LDS reads of four column
+            // steps issued together, then their products in column order
+            int st = 0;
+            for (; st + 4 <= steps; st += 4) {
+                float bq[4], aq[NTILE][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = 4 * (st + u) + lk;
+                    bq[u] = fr[col];
+#pragma unroll
+                    for (int t = 0; t < NTILE; ++t) aq[t][u] = Cs[(16 * t + li) * RP + col];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    nf += (double)bq[u] * (double)bq[u];
+#pragma unroll
+                    for (int t = 0; t < NTILE; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[t][u], bq[u], acc[t], 0, 0, 0);
+                }
+            }
+            for (; st < steps; ++st) {
                 const int col = 4 * st + lk;
-                const float b = (live && col < r) ? fr[col] : 0.0f;
+                const float b = fr[col];
                 nf += (double)b * (double)b;
 #pragma unroll
                 for (int t = 0; t < NTILE; ++t) {
@@ -501,7 +544,7 @@ __global__ __launch_bounds__(NT) void assign_grouped_kernel(const float *__restr
 #pragma clang fp contract(off)
     extern __shared__ double Cd[];
     constexpr int RPW = 64 / KP;
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     Cg += blockIdx.y * bt.c;
     labels += blockIdx.y * bt.l;
     if (dist2) dist2 += blockIdx.y * bt.l;
@@ -565,7 +608,7 @@ __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, in
                                       double *__restrict__ part, int64_t *__restrict__ pcount, Bat bt) {
     extern __shared__ double S[];  // k*r sums then k counts (as double)
     const int64_t kr = (int64_t)k * r;
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     labels += blockIdx.y * bt.l;
     part += (int64_t)blockIdx.y * gridDim.x * kr;
     pcount += (int64_t)blockIdx.y * gridDim.x * k;
@@ -620,7 +663,7 @@ __global__ __launch_bounds__(256) void update_partial4_kernel(const float *__res
     extern __shared__ double S4[];  // 4 x (k*r sums, k counts)
     const int64_t kr = (int64_t)k * r;
     const int64_t stride = kr + k;
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     labels += blockIdx.y * bt.l;
     part += (int64_t)blockIdx.y * gridDim.x * kr;
     pcount += (int64_t)blockIdx.y * gridDim.x * k;
@@ -688,7 +731,7 @@ __global__ __launch_bounds__(256) void update_slots_kernel(const float *__restri
     const int ncopy = 4 * SL;
     const int64_t kr = (int64_t)k * r;
     const int64_t stride = kr + k;
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     labels += blockIdx.y * bt.l;
     part += (int64_t)blockIdx.y * gridDim.x * kr;
     pcount += (int64_t)blockIdx.y * gridDim.x * k;
@@ -749,7 +792,7 @@ __global__ void update_partial_global_kernel(const float *__restrict__ F, int64_
                                              const int32_t *__restrict__ labels, int k, int64_t rows_per_block,
                                              double *__restrict__ part, int64_t *__restrict__ pcount, Bat bt) {
     const int64_t kr = (int64_t)k * r;
-    F += fblk(bt);
+    F += fblk(bt, blockIdx.y);
     labels += blockIdx.y * bt.l;
     part += (int64_t)blockIdx.y * gridDim.x * kr;
     pcount += (int64_t)blockIdx.y * gridDim.x * k;
@@ -796,6 +839,44 @@ __global__ void update_final_kernel(int nblocks, int64_t r, int k, const double 
             if (cnt > 0) C[q] = (float)(s / (double)cnt);
             if (counts && q - (int64_t)c * r == 0) counts[c] = cnt;
         }
+    }
+}
+
+// Up to W <= 32 partial blocks: one lane per (c, col) instead of one
+// wavefront.  The lane holds the W partial sums (zero past nblocks) and adds
+// them in registers by the pairing of the butterfly above: lane l of the
+// wavefront adds lane l + off for off = 32, 16, ..., 1, and the levels with
+// off >= W only add zeros to the canonical 0.0 + p of each lane, so the
+// result is the butterfly's, bit for bit.
+template <int W>
+__global__ __launch_bounds__(256) void update_final_lanes_kernel(int nblocks, int64_t r, int k,
+                                                                 const double *__restrict__ part,
+                                                                 const int64_t *__restrict__ pcount,
+                                                                 float *__restrict__ C, int64_t *__restrict__ counts,
+                                                                 Bat bt) {
+    const int64_t kr = (int64_t)k * r;
+    part += (int64_t)blockIdx.y * nblocks * kr;
+    pcount += (int64_t)blockIdx.y * nblocks * k;
+    C += blockIdx.y * bt.c;
+    if (counts) counts += (int64_t)blockIdx.y * k;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < kr; q += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(q / r);
+        double v[W];
+        int64_t cnt = 0;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            const bool in = b < nblocks;
+            const double x = part[(int64_t)(in ? b : 0) * kr + q];
+            const int64_t m = pcount[(int64_t)(in ? b : 0) * k + c];
+            v[b] = in ? 0.0 + x : 0.0;
+            cnt += in ? m : 0;
+        }
+#pragma unroll
+        for (int off = W / 2; off >= 1; off >>= 1)
+#pragma unroll
+            for (int l = 0; l < off; ++l) v[l] = v[l] + v[l + off];
+        if (cnt > 0) C[q] = (float)(v[0] / (double)cnt);
+        if (counts && q - (int64_t)c * r == 0) counts[c] = cnt;
     }
 }
 
@@ -849,14 +930,24 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
                  float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
     constexpr int KC = 16 * NTILE;
     const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
-    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NTILE <= 2 ? (NT / 64) * 16 : 0)) * rp * sizeof(float);
+    // rows staged in LDS for batches of problems up to 32 centroids (measured
+    // faster there); one large problem reads its rows from F, with the loads
+    // of the next column steps in flight (1.6x faster at 1e6 x 96, k = 20)
+    const bool stage = NTILE <= 2 && b.count > 1;
+    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (stage ? (NT / 64) * 16 : 0)) * rp * sizeof(float);
     // many small problems: about 8 row groups per wavefront, so the centroid
     // staging of a block is spread over more rows
     const int64_t rows_per_block = (NT / 64) * 16 * (b.count > 1 ? 8 : 1);
     const int64_t want = (n + rows_per_block - 1) / rows_per_block;
     const int64_t cap = b.count <= 1 ? 8192 : std::max<int64_t>(1, 65536 / b.count);
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
-    assign_mfma_kernel<NTILE><<<grid, NT, lds, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
+    if constexpr (NTILE <= 2) {
+        if (stage) {
+            assign_mfma_kernel<NTILE, true><<<grid, NT, lds, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
+            return;
+        }
+    }
+    assign_mfma_kernel<NTILE, false><<<grid, NT, lds, s>>>(F, n, r, ldf, C, k, labels, dist2, dist64, to_bat(b));
 }
 
 void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
@@ -865,7 +956,7 @@ void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C
     // rows) fit 64 KB of LDS
     const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
     const int kc = ((k + 15) / 16) * 16;
-    const int staged = kc <= 32 ? 64 : 0;
+    const int staged = kc <= 32 && b.count > 1 ? 64 : 0;
     if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + staged) * rpad * 4 <= 64 * 1024) {
         switch ((k + 15) / 16) {
             case 1: assign_mfma<1>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
@@ -933,8 +1024,18 @@ void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t 
     else
         update_partial_global_kernel<<<g1, threads, 0, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
     const int64_t kr = (int64_t)k * r;
-    const int64_t want = (kr * 64 + 255) / 256;
     const int64_t cap = b.count <= 1 ? 4096 : std::max<int64_t>(1, 65536 / b.count);
+    if (nb <= 32) {
+        const dim3 gl((unsigned)std::max<int64_t>(1, std::min((kr + 255) / 256, cap)), (unsigned)b.count);
+        if (nb <= 8)
+            update_final_lanes_kernel<8><<<gl, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
+        else if (nb <= 16)
+            update_final_lanes_kernel<16><<<gl, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
+        else
+            update_final_lanes_kernel<32><<<gl, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
+        return;
+    }
+    const int64_t want = (kr * 64 + 255) / 256;
     const dim3 g2((unsigned)std::max<int64_t>(1, std::min(want, cap)), (unsigned)b.count);
     update_final_kernel<<<g2, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
 }
