@@ -165,6 +165,61 @@ __global__ __launch_bounds__(NT) void stab_combine_kernel(int64_t n, int rs, con
     }
 }
 
+// The same features for every k at once (up to 32 values of k), from one
+// read of the store instead of one per k: a lane keeps one float32
+// accumulator per k and adds, for t in order, fma(a_{k,j,t}, T_t[i][col])
+// exactly as stab_combine_kernel does for one k (identical features).  The
+// coefficients come from cfT[j][t][u] = (float) a_{u,j,t} (zero for u >= nk),
+// the same at every lane of a block, so they are scalar loads.
+constexpr int kCombineAllMax = 32;
+struct CombineAll {
+    int nk;
+    int eta[kCombineAllMax];
+    int ld[kCombineAllMax];
+    int64_t off[kCombineAllMax];  // element offset of the block of k_min + u in Y, laid out [J][n][ld]
+};
+
+__global__ void stab_cf_table_kernel(const double *__restrict__ coeffs, int nk, int J, int p, float *__restrict__ cfT) {
+    const int64_t total = (int64_t)J * (p + 1) * kCombineAllMax;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int u = (int)(q % kCombineAllMax);
+        const int64_t jt = q / kCombineAllMax;  // j (p + 1) + t
+        const int j = (int)(jt / (p + 1));
+        const int t = (int)(jt - (int64_t)j * (p + 1));
+        cfT[q] = u < nk ? (float)coeffs[((int64_t)u * J + j) * (p + 1) + t] : 0.0f;
+    }
+}
+
+template <typename TS, int NKC>
+__global__ __launch_bounds__(NT) void stab_combine_all_kernel(int64_t n, int rs, const TS *__restrict__ store,
+                                                              int64_t slot_elems, int p, int64_t eta_max,
+                                                              int eta_used, const float *__restrict__ cfT,
+                                                              float *__restrict__ Y, CombineAll ca) {
+    const int j = blockIdx.y;
+    const float *cfj = cfT + (int64_t)j * (p + 1) * kCombineAllMax;
+    const int64_t total = n * eta_used;
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < total; q += (int64_t)gridDim.x * NT) {
+        const int64_t i = q / eta_used;
+        const int c = (int)(q - i * eta_used);
+        const int64_t col = (int64_t)j * eta_max + c;
+        const int64_t sl = col / rs;
+        const int64_t cc = col - sl * rs;
+        const TS *src = store + sl * (p + 1) * slot_elems + i * rs + cc;
+        float acc[NKC];
+#pragma unroll
+        for (int u = 0; u < NKC; ++u) acc[u] = 0.0f;
+        for (int t = 0; t <= p; ++t) {
+            const float x = elem_f32(src[(int64_t)t * slot_elems]);
+            const float *cf = cfj + (int64_t)t * kCombineAllMax;
+#pragma unroll
+            for (int u = 0; u < NKC; ++u) acc[u] = fmaf(cf[u], x, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NKC; ++u)
+            if (u < ca.nk && c < ca.eta[u]) Y[ca.off[u] + ((int64_t)j * n + i) * ca.ld[u] + c] = acc[u];
+    }
+}
+
 // one block per realisation: inertia of every replicate (float64, fixed
 // order), the least one (lowest replicate on ties) gives the labels
 __global__ __launch_bounds__(NT) void select_kernel(const double *__restrict__ dist64,
@@ -309,6 +364,7 @@ struct StabWs {
     double *lam;
     double *coeffs;
     float *Y;
+    float *cfT;  // all-k coefficient table (when every k's features are formed at once)
     float *C;
     int32_t *lab_all;
     double *dist64;
@@ -323,6 +379,8 @@ struct StabDims {
     int64_t eta_max;
     int nchunks;
     StoreLayout S;
+    bool all_k;      // every k's features formed in one pass over the store
+    int64_t ld_sum;  // sum over k of the feature leading dimensions
 };
 
 size_t stab_ws_layout(const asc_graph *g, const StabDims &d, asc_dtype sig, void *ws, StabWs *out) {
@@ -341,7 +399,8 @@ size_t stab_ws_layout(const asc_graph *g, const StabDims &d, asc_dtype sig, void
     w.M = a.take<double>((size_t)d.nk * d.J * (d.p + 1));
     w.lam = a.take<double>((size_t)d.nk * d.J);
     w.coeffs = a.take<double>((size_t)d.nk * d.J * (d.p + 1));
-    w.Y = a.take<float>((size_t)d.J * n * ldmax);
+    w.Y = a.take<float>((size_t)d.J * n * (d.all_k ? d.ld_sum : ldmax));
+    w.cfT = d.all_k ? a.take<float>((size_t)d.J * (d.p + 1) * kCombineAllMax) : nullptr;
     w.C = a.take<float>((size_t)d.J * d.reps * d.kmax * d.etamax_used);
     w.lab_all = a.take<int32_t>((size_t)d.J * d.reps * n);
     w.dist64 = a.take<double>((size_t)d.J * d.reps * n);
@@ -384,6 +443,10 @@ asc_status stab_dims(const asc_graph *g, int k_min, int k_max, const int *eta, i
     d->eta_max = eta_max;
     d->nchunks = (int)std::max<int64_t>(1, (g->n + kChunkRows - 1) / kChunkRows);
     d->S = store_layout(g, d->C, sig);
+    d->ld_sum = 0;
+    for (int q = 0; q < d->nk; ++q) d->ld_sum += ((int64_t)eta[q] + 3) & ~int64_t(3);
+    // all k at once while the coefficient table stays small (a few MB)
+    d->all_k = d->nk <= kCombineAllMax && (size_t)J * (p + 1) * kCombineAllMax * sizeof(float) <= (size_t(64) << 20);
     return ASC_OK;
 }
 
@@ -403,6 +466,36 @@ void launch_combine(const StabDims &d, const StabWs &w, int eta, const double *c
     const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, std::max(1, 16384 / d.J)));
     stab_combine_kernel<TS><<<dim3((unsigned)bx, (unsigned)d.J), NT, (size_t)(d.p + 1) * sizeof(float), s>>>(
         d.n, d.S.rs, static_cast<const TS *>(w.store), slot_elems, d.p, d.eta_max, eta, coeffs_k, w.Y, ldy);
+}
+
+// every k's features in one pass (d.all_k); offsets of the per-k blocks in ca
+template <typename TS>
+void launch_combine_all(const StabDims &d, const StabWs &w, const int *eta_host, CombineAll &ca, hipStream_t s) {
+    ca.nk = d.nk;
+    int64_t off = 0;
+    for (int u = 0; u < d.nk; ++u) {
+        ca.eta[u] = eta_host[u];
+        ca.ld[u] = (eta_host[u] + 3) & ~3;
+        ca.off[u] = off;
+        off += (int64_t)d.J * d.n * ca.ld[u];
+    }
+    const int64_t tcf = (int64_t)d.J * (d.p + 1) * kCombineAllMax;
+    stab_cf_table_kernel<<<(unsigned)std::min<int64_t>((tcf + 255) / 256, 16384), 256, 0, s>>>(w.coeffs, d.nk, d.J,
+                                                                                              d.p, w.cfT);
+    const int64_t slot_elems = (int64_t)(d.S.panel_bytes / sizeof(TS));
+    const int64_t total = d.n * d.etamax_used;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, std::max(1, 16384 / d.J))),
+                    (unsigned)d.J);
+    const TS *st = static_cast<const TS *>(w.store);
+    if (d.nk <= 8)
+        stab_combine_all_kernel<TS, 8><<<grid, NT, 0, s>>>(d.n, d.S.rs, st, slot_elems, d.p, d.eta_max,
+                                                           d.etamax_used, w.cfT, w.Y, ca);
+    else if (d.nk <= 16)
+        stab_combine_all_kernel<TS, 16><<<grid, NT, 0, s>>>(d.n, d.S.rs, st, slot_elems, d.p, d.eta_max,
+                                                            d.etamax_used, w.cfT, w.Y, ca);
+    else
+        stab_combine_all_kernel<TS, 32><<<grid, NT, 0, s>>>(d.n, d.S.rs, st, slot_elems, d.p, d.eta_max,
+                                                            d.etamax_used, w.cfT, w.Y, ca);
 }
 
 }  // namespace
@@ -462,16 +555,26 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
     stab_dichotomy_kernel<<<dim3((unsigned)J, (unsigned)d.nk), NT, 0, s>>>(w.M, p, lmax, k_min, J, steps, lam, traj,
                                                                           w.coeffs);
     ASC_LAUNCHED();
-    // 3. per k: features, normalisation, batched k-means, selection, ARIs
+    // 3. features: every k's at once, or one k at a time below
+    CombineAll ca{};
+    if (d.all_k) {
+        if (sig == ASC_F32) launch_combine_all<float>(d, w, eta_host, ca, s);
+        else launch_combine_all<uint16_t>(d, w, eta_host, ca, s);
+        ASC_LAUNCHED();
+    }
+    // 4. per k: (features,) normalisation, batched k-means, selection, ARIs
     for (int kk = 0; kk < d.nk; ++kk) {
         const int k = k_min + kk;
         const int eta = eta_host[kk];
         const int64_t ld = ((int64_t)eta + 3) & ~int64_t(3);
-        const double *co = w.coeffs + (int64_t)kk * J * (p + 1);
-        if (sig == ASC_F32) launch_combine<float>(d, w, eta, co, ld, s);
-        else launch_combine<uint16_t>(d, w, eta, co, ld, s);
-        ASC_LAUNCHED();
-        km_normalize(w.Y, (int64_t)J * n, eta, ld, nullptr, s);
+        float *Yk = d.all_k ? w.Y + ca.off[kk] : w.Y;
+        if (!d.all_k) {
+            const double *co = w.coeffs + (int64_t)kk * J * (p + 1);
+            if (sig == ASC_F32) launch_combine<float>(d, w, eta, co, ld, s);
+            else launch_combine<uint16_t>(d, w, eta, co, ld, s);
+            ASC_LAUNCHED();
+        }
+        km_normalize(Yk, (int64_t)J * n, eta, ld, nullptr, s);
         ASC_LAUNCHED();
         KmBatch b;
         b.count = J * reps;
@@ -481,15 +584,15 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         b.lstride = n;
         b.rows_stride = k_max;
         const int32_t *rows_k = init_rows + (int64_t)kk * J * reps * k_max;
-        km_init_rows(w.Y, n, eta, ld, rows_k, k, w.C, b, s);
+        km_init_rows(Yk, n, eta, ld, rows_k, k, w.C, b, s);
         ASC_LAUNCHED();
         for (int it = 0; it < kmeans_iters; ++it) {
-            km_assign(w.Y, n, eta, ld, w.C, k, w.lab_all, nullptr, nullptr, b, s);
+            km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, nullptr, b, s);
             ASC_LAUNCHED();
-            km_update(w.Y, n, eta, ld, w.lab_all, k, w.C, nullptr, w.kmws, b, s);
+            km_update(Yk, n, eta, ld, w.lab_all, k, w.C, nullptr, w.kmws, b, s);
             ASC_LAUNCHED();
         }
-        km_assign(w.Y, n, eta, ld, w.C, k, w.lab_all, nullptr, w.dist64, b, s);
+        km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, w.dist64, b, s);
         ASC_LAUNCHED();
         int32_t *lab_k = labels ? labels + (int64_t)kk * J * n : w.labels;
         select_kernel<<<J, NT, 0, s>>>(w.dist64, w.lab_all, n, reps, lab_k,
