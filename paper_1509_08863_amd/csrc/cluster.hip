@@ -299,11 +299,13 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     const int li = lane & 15, lk = lane >> 4;
     const int steps = (int)((r + 3) >> 2);
     const double ecoef = 3.0 * (double)(r + 2) * 0x1p-24;
-    // staged rows: element q = rl * RP + col of the wavefront's 16 LDS rows;
-    // lane q0 + lane starts at (rl0, col0), and each further load is 64
-    // elements on, (d64, m64) rows and columns (no division per element)
-    const int rl0 = lane / RP, col0 = lane - rl0 * RP;
-    const int d64 = 64 / RP, m64 = 64 - d64 * RP;
+    // staged rows, in 16-byte quads (rows of F 16-byte aligned when staged):
+    // quad qd = rl * NQ + cq of the wavefront's 16 rows; lane qd0 + lane starts
+    // at (qr0, qc0), and each further load is 64 quads on, (dq64, mq64) rows
+    // and quads (no division per load)
+    const int NQ = (int)((r + 3) >> 2);
+    const int qr0 = lane / NQ, qc0 = lane - qr0 * NQ;
+    const int dq64 = 64 / NQ, mq64 = 64 - dq64 * NQ;
     const int64_t wave0 = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * NT) >> 6;
     for (int64_t g = wave0; g * 16 < n; g += nwaves) {
@@ -314,29 +316,37 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
         // hide the loads behind); above, each lane reads its row from F
         const float *fr;
         if constexpr (kStageRows) {
-            // four loads in flight per lane, from clamped in-range addresses and
-            // always issued, then their LDS stores; zero past r and past n
+            // four 16-byte loads in flight per lane, from clamped in-range
+            // addresses and always issued, then their LDS stores; zero past r
+            // and past n (the odd pad column RP - 1 is never read)
             const int64_t left = n - g * 16;  // rows of this group that exist (>= 1)
-            const float *fg = F + g * 16 * ldf;
-            int rl = rl0, col = col0;
-            for (int q0 = 0; q0 < 16 * RP; q0 += 4 * 64) {
-                float v[4];
+            const v4f *fg = reinterpret_cast<const v4f *>(F + g * 16 * ldf);
+            const int64_t ldq = ldf >> 2;
+            int rl = qr0, cq = qc0;
+            for (int q0 = 0; q0 < 16 * NQ; q0 += 4 * 64) {
+                v4f v[4];
+                int row[4], c4[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const bool in = rl < 16 && rl < left && col < r;
-                    const float x = fg[in ? (int64_t)rl * ldf + col : 0];
-                    v[u] = in ? x : 0.0f;
-                    rl += d64;
-                    col += m64;
-                    if (col >= RP) {
-                        col -= RP;
+                    const bool in = rl < 16 && rl < left;
+                    const v4f x = fg[in ? (int64_t)rl * ldq + cq : 0];
+                    v[u] = in ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                    row[u] = rl;
+                    c4[u] = 4 * cq;
+                    rl += dq64;
+                    cq += mq64;
+                    if (cq >= NQ) {
+                        cq -= NQ;
                         ++rl;
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int q = q0 + u * 64 + lane;
-                    if (q < 16 * RP) Fs[q] = v[u];
+                    if (row[u] < 16) {
+                        float *d = Fs + row[u] * RP + c4[u];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) d[e] = c4[u] + e < r ? v[u][e] : 0.0f;
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -925,6 +935,11 @@ void assign_grouped(const float *F, int64_t n, int64_t r, int64_t ldf, const flo
                                                                                dist64, to_bat(b));
 }
 
+// rows are staged with 16-byte loads: every problem's feature rows 16-byte aligned
+static bool stage_ok(const float *F, int64_t ldf, const KmBatch &b) {
+    return aligned(F, 16) && ldf % 4 == 0 && b.fstride % 4 == 0;
+}
+
 template <int NTILE>
 void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                  float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
@@ -933,7 +948,7 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
     // rows staged in LDS for batches of problems up to 32 centroids (measured
     // faster there); one large problem reads its rows from F, with the loads
     // of the next column steps in flight (1.6x faster at 1e6 x 96, k = 20)
-    const bool stage = NTILE <= 2 && b.count > 1;
+    const bool stage = NTILE <= 2 && b.count > 1 && stage_ok(F, ldf, b);
     const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (stage ? (NT / 64) * 16 : 0)) * rp * sizeof(float);
     // many small problems: about 8 row groups per wavefront, so the centroid
     // staging of a block is spread over more rows
@@ -956,7 +971,7 @@ void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C
     // rows) fit 64 KB of LDS
     const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
     const int kc = ((k + 15) / 16) * 16;
-    const int staged = kc <= 32 && b.count > 1 ? 64 : 0;
+    const int staged = kc <= 32 && b.count > 1 && stage_ok(F, ldf, b) ? 64 : 0;
     if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + staged) * rpad * 4 <= 64 * 1024) {
         switch ((k + 15) / 16) {
             case 1: assign_mfma<1>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
