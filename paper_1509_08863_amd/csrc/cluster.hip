@@ -1032,7 +1032,7 @@ void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t 
     if (b.count > 1 && rs <= 32 && (size_t)4 * (64 / rs) * lds <= 64 * 1024)
         update_slots_kernel<<<g1, 256, (size_t)4 * (64 / rs) * lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount,
                                                                           to_bat(b), rs);
-    else if (b.count > 1 && 4 * lds <= 64 * 1024)
+    else if (4 * lds <= 64 * 1024)
         update_partial4_kernel<<<g1, 256, 4 * lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
     else if (lds <= 64 * 1024)
         update_partial_kernel<<<g1, threads, lds, s>>>(F, n, r, ldf, labels, k, rpb, part, pcount, to_bat(b));
