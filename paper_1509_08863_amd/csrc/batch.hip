@@ -243,8 +243,8 @@ void retile(BatchPlan &b, const Plan &P, int tile_rows) {
     }
     b.grid = (int)std::max<size_t>(1, std::min<size_t>(b.tiles.size(), kMaxGrid));
     b.uploaded_ws = nullptr;
-    if (b.exec) hipGraphExecDestroy(b.exec);
-    if (b.graph) hipGraphDestroy(b.graph);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
 }
@@ -461,7 +461,7 @@ extern "C" asc_status asc_batch_autotune(void *plan, const double *lmax, const v
     hipEvent_t e0, e1;
     ASC_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(ASC_ERR_HIP, "%s: event creation failed", who);
     }
     Plan bestP = b.P;
