@@ -492,8 +492,8 @@ extern "C" asc_status asc_batch_autotune(void *plan, const double *lmax, const v
             bestTR = t.tile_rows;
         }
     });
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != ASC_OK) return st;
     retile(b, bestP, bestTR);
     if (best_slice_cols) *best_slice_cols = bestP.rs;
@@ -518,33 +518,33 @@ extern "C" asc_status asc_batch_run(void *plan, const double *lmax, const void *
     for (int q = 0; q < 8 && same; ++q) same = key[q] == b.cap_key[q];
     if (!same) {
         if (b.exec) {
-            hipGraphExecDestroy(b.exec);
+            (void)hipGraphExecDestroy(b.exec);
             b.exec = nullptr;
         }
         if (b.graph) {
-            hipGraphDestroy(b.graph);
+            (void)hipGraphDestroy(b.graph);
             b.graph = nullptr;
         }
         hipStream_t cs;
         ASC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
-            hipStreamDestroy(cs);
+            (void)hipStreamDestroy(cs);
             return fail(ASC_ERR_HIP, "%s: capture failed: %s", who, hipGetErrorString(e));
         }
         asc_status st = enqueue_batch(b, lmax, R, ldr, Y, ldy, lambda_k, traj, ws, cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (st != ASC_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return st;
         }
         if (e != hipSuccess) return fail(ASC_ERR_HIP, "%s: end capture failed: %s", who, hipGetErrorString(e));
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return fail(ASC_ERR_HIP, "%s: graph instantiate failed: %s", who, hipGetErrorString(e));
         }
         b.graph = graph;
@@ -558,8 +558,8 @@ extern "C" asc_status asc_batch_run(void *plan, const double *lmax, const void *
 extern "C" asc_status asc_batch_destroy(void *plan) {
     if (!plan) return ASC_OK;
     BatchPlan *b = static_cast<BatchPlan *>(plan);
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     delete b;
     return ASC_OK;
 }
