@@ -172,3 +172,28 @@ def test_stability_full_benchmark_size_sampled():
         assert np.min(res["inertia"][q, j]) == pytest.approx(np.min(ins), rel=1e-4)
         agree.append(oracle.ari(res["labels"][q, j], lab))
     assert np.mean(agree) >= 0.97, agree
+
+
+def test_features_of_every_k_at_once_equal_one_k_at_a_time():
+    # up to 32 values of k the sweep forms every k's features in one pass over
+    # the state store, above that one k at a time; on the same signals (same
+    # eta_max, so the same realisations) and initial rows the overlapping k
+    # must give bit-identical estimates, labels and gamma
+    x, _ = W.gmm2d_points(1000, 5, 91)
+    g = W.knn_graph(x, int(round(np.log(1000))))
+    J, reps, p, steps, iters, eta_max = 3, 2, 40, 8, 5, 72
+    Rs, _ = W.stability_pools(g.n, J, eta_max, 41)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, None)
+    lmax = 1.01 * oracle.lambda_max_exact(L)
+    G = upload_graph(g)
+    out = {}
+    for ks in (list(range(2, 37)), list(range(2, 21))):
+        rows = W.stability_init_rows(g.n, ks, J, reps, 42)
+        res = asc.stability(G, scalar(lmax), ks[0], ks[-1], [2 * k for k in ks], J, reps, p, steps, iters,
+                            block_f32(Rs), eta_max, to_dev(rows))
+        out[len(ks)] = {k_: host(v) for k_, v in res.items()}
+    per_k, all_k = out[35], out[19]
+    np.testing.assert_array_equal(per_k["lambda_k"][:19], all_k["lambda_k"])
+    np.testing.assert_array_equal(per_k["labels"][:19], all_k["labels"])
+    np.testing.assert_array_equal(per_k["inertia"][:19], all_k["inertia"])
+    np.testing.assert_array_equal(per_k["gamma"][:19], all_k["gamma"])
