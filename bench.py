@@ -309,11 +309,13 @@ def extra_stability(dev, c=6, reps_timed=3):
     ws = asc.stability.last_ws
     ms = _time(lambda: asc.stability(*args, ws=ws), reps_timed)
     out = asc.stability(*args, ws=ws)
+    flags = asc.read_flags(ws, raise_on_error=False)
     gam = out["gamma"].cpu().numpy()
     res = {"workload": cfg["name"], "n": g.n, "nnz": g.nnz, "ks": [ks[0], ks[-1]], "J": J, "reps": cfg["reps"],
            "p": cfg["p"], "kmeans_iters": cfg["kmeans_iters"], "ms_per_sweep": round(ms, 3),
            "gamma": [round(float(x), 4) for x in gam], "k_star": int(ks[int(np.argmax(gam))]),
-           "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1)}
+           "k_true": cfg["k_true"], "workspace_gb": round(ws.numel() / 1e9, 2), "gen_s": round(gen_s, 1),
+           "health": flags}
     if cfg["n"] <= 10_000:
         # the oracle on one (k, realisation) cell at the middle k, scaled to the sweep
         import oracle
@@ -508,7 +510,9 @@ def parse():
                     help="node order of the graph (block: each generating block contiguous)")
     ap.add_argument("--no-pattern", action="store_true", help="skip the pattern-only (w = NULL) filter timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default tiling)")
-    ap.add_argument("--extra", action="store_true", help="also time the batched workload and the kNN gradients")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the kNN graph build and the gamma(k) sweep on the 1e5-point mixture")
+    ap.add_argument("--no-stability", action="store_true", help="skip the gamma(k) sweep on the 5000-point mixture")
     ap.add_argument("--copy-probe", action="store_true", help="only time the plain 2 GiB copy kernel and exit")
     ap.add_argument("--knn-only", action="store_true", help="only time the kNN graph construction and exit")
     ap.add_argument("--batch-only", action="store_true", help="only time the 64-graph batch and exit")
@@ -913,6 +917,13 @@ def main():
         _progress("kNN gradients done")
     else:
         knn_res = None
+    # the stability measure gamma(k) over k = 2..20 (Sec. 4.3, the paper's
+    # Fig. 2 setting on the planar-mixture stand-in)
+    stab_res = None
+    if not args.no_stability:
+        stab_res = extra_stability(dev, 6)
+        health["stability"] = stab_res.pop("health")
+        _progress(f"stability sweep {stab_res['ms_per_sweep']:.1f} ms")
     # the same graph with every generating block contiguous (the generator's
     # labels: the best node order a partitioner could find), the filter alone;
     # run last because its tuning entry replaces this graph size's entry
@@ -942,8 +953,7 @@ def main():
         _progress(f"block order filter {ms_b:.1f} ms")
     extra = None
     if args.extra:
-        parts = [("knn_build", lambda: extra_knn_build(dev)), ("stability", lambda: extra_stability(dev, 6)),
-                 ("stability_large", lambda: extra_stability(dev, 7, 1))]
+        parts = [("knn_build", lambda: extra_knn_build(dev)), ("stability_large", lambda: extra_stability(dev, 7, 1))]
         extra = {}
         for name, fn in parts:
             extra[name] = fn()
@@ -1003,6 +1013,7 @@ def main():
         "sbm_n1e5": mid_res,
         "batch": batch_res,
         "knn_grad": knn_res,
+        "stability": stab_res,
         "health": {"flags": health,
                    "ok": all((f & (asc._abi.ASC_FLAG_GROWTH | asc._abi.ASC_FLAG_NONFINITE)) == 0
                              for f in health.values())},
