@@ -104,6 +104,73 @@ __global__ __launch_bounds__(NT) void pp_dist_kernel(const float *__restrict__ F
     }
 }
 
+// The same pass for rows of 16-byte aligned quads (r and ldf multiples of 4):
+// a wavefront takes 64 rows and brings them in through LDS, 32 columns at a
+// time, with coalesced 16-byte loads (8 rows x 128 bytes per load instead of
+// one 16-byte piece of 64 different rows); each lane then adds its own row's
+// squared differences in column order, exactly as above.
+constexpr int kPpChunk = 32;
+__global__ __launch_bounds__(NT) void pp_dist_staged_kernel(const float *__restrict__ F, int64_t n, int64_t r,
+                                                            int64_t ldf, const int32_t *__restrict__ rows, int c,
+                                                            double *__restrict__ D, double *__restrict__ pmax) {
+#pragma clang fp contract(off)
+    __shared__ float Xs[NT / 64][64][kPpChunk + 1];  // +1: lane l reads row l without bank conflicts
+    __shared__ double red[NT / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float *x = F + (int64_t)rows[c] * ldf;
+    float(*S)[kPpChunk + 1] = Xs[wave];
+    const int64_t ldq = ldf >> 2;
+    double m = 0.0;
+    for (int64_t base = ((int64_t)blockIdx.x * (NT / 64) + wave) * 64; base < n;
+         base += (int64_t)gridDim.x * (NT / 64) * 64) {
+        const int64_t i = base + lane;
+        double d = 0.0;
+        for (int64_t c0 = 0; c0 < r; c0 += kPpChunk) {
+            const int w = (int)min<int64_t>(kPpChunk, r - c0);  // a multiple of 4
+            const float4 *g4 = reinterpret_cast<const float4 *>(F + base * ldf + c0);
+            // quad e of the chunk: row e >> 3, quad e & 7 (8 quads of a 32-column row)
+            float4 v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int e = t * 64 + lane;
+                const int rl = e >> 3, cq = e & 7;
+                const bool in = base + rl < n && 4 * cq < w;
+                const float4 a = g4[in ? (int64_t)rl * ldq + cq : 0];
+                v[t] = in ? a : float4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int e = t * 64 + lane;
+                const int rl = e >> 3, cq = e & 7;
+                S[rl][4 * cq + 0] = v[t].x;
+                S[rl][4 * cq + 1] = v[t].y;
+                S[rl][4 * cq + 2] = v[t].z;
+                S[rl][4 * cq + 3] = v[t].w;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int col = 0; col < w; ++col) {
+                const double diff = (double)S[lane][col] - (double)x[c0 + col];
+                const double sq = diff * diff;
+                d = d + sq;
+            }
+            __builtin_amdgcn_wave_barrier();  // S is free for the next chunk
+        }
+        if (i < n) {
+            const double v = (c == 0 || d < D[i]) ? d : D[i];
+            D[i] = v;
+            m = fmax(m, v);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[w]);
+        pmax[blockIdx.x] = v;
+    }
+}
+
 // dmax[0] = the largest of the distance pass's block maxima
 __global__ __launch_bounds__(NT) void pp_max_kernel(const double *__restrict__ pmax, int np, double *__restrict__ dmax) {
     const double m = block_max(pmax, np);
@@ -139,17 +206,34 @@ __global__ __launch_bounds__(NT) void pp_pick_kernel(const double *__restrict__ 
     __shared__ int sh_found;
     const double dmax = dmaxp[0];
     const uint64_t u = U[c] & kUMask;
+    // T and the block whose prefix passes the target, by a block-wide scan:
+    // thread t owns the contiguous blocks [t P, t P + P) (integer sums, so
+    // the result is the sequential scan's)
+    __shared__ int64_t tsum[NT];
+    const int P = (nb + NT - 1) / NT;
+    const int b0 = threadIdx.x * P, b1 = min(nb, b0 + P);
+    int64_t own = 0;
+    for (int b = b0; b < b1; ++b) own += bsum[b];
+    tsum[threadIdx.x] = own;
     if (threadIdx.x == 0) {
-        int64_t T = 0;
-        for (int b = 0; b < nb; ++b) T += bsum[b];
         sh_block = -1;
         sh_found = 0;
-        if (T == 0) {
-            rows[c] = (int32_t)mulshift53(u, (uint64_t)n);
-        } else {
-            const int64_t target = (int64_t)mulshift53(u, (uint64_t)T);
-            int64_t acc = 0;
-            for (int b = 0; b < nb; ++b) {
+    }
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {  // inclusive scan of the owners' sums
+        const int64_t add = threadIdx.x >= off ? tsum[threadIdx.x - off] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int64_t T = tsum[NT - 1];
+    if (T == 0) {
+        if (threadIdx.x == 0) rows[c] = (int32_t)mulshift53(u, (uint64_t)n);
+    } else {
+        const int64_t target = (int64_t)mulshift53(u, (uint64_t)T);
+        int64_t acc = tsum[threadIdx.x] - own;  // the sum over the blocks before b0
+        if (acc <= target && target < acc + own) {
+            for (int b = b0; b < b1; ++b) {
                 if (acc + bsum[b] > target) {
                     sh_block = b;
                     sh_base = target - acc;  // the row is where the block's own prefix passes this
@@ -223,7 +307,10 @@ extern "C" asc_status asc_kmeanspp(const float *F, int64_t n, int64_t r, int64_t
     pp_first_kernel<<<1, 64, 0, s>>>(U, n, rows);
     ASC_LAUNCHED();
     for (int c = 0; c + 1 < k; ++c) {
-        pp_dist_kernel<<<nd, NT, 0, s>>>(F, n, r, ldf, vec4, rows, c, D, pmax);
+        if (vec4)
+            pp_dist_staged_kernel<<<nd, NT, 0, s>>>(F, n, r, ldf, rows, c, D, pmax);
+        else
+            pp_dist_kernel<<<nd, NT, 0, s>>>(F, n, r, ldf, vec4, rows, c, D, pmax);
         ASC_LAUNCHED();
         pp_max_kernel<<<1, NT, 0, s>>>(pmax, nd, dmax);
         ASC_LAUNCHED();

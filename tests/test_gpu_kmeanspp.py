@@ -17,7 +17,8 @@ def _u(k, seed):
     return torch.from_numpy(W.seeding_draws(k, seed).astype(np.int64)).to(DEV)
 
 
-@pytest.mark.parametrize("n,r,k", [(1000, 8, 10), (4099, 33, 64), (300_001, 16, 20), (257, 3, 257), (5, 2, 1)])
+@pytest.mark.parametrize("n,r,k", [(1000, 8, 10), (4099, 33, 64), (300_001, 16, 20), (257, 3, 257), (5, 2, 1),
+                                   (2049, 40, 30), (1500, 100, 50), (70, 64, 64)])
 def test_kmeanspp_rows_match_oracle(n, r, k):
     rng = np.random.default_rng(n + k)
     F = rng.standard_normal((n, r)).astype(np.float32)
