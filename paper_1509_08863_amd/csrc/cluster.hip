@@ -945,11 +945,14 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
                  float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
     constexpr int KC = 16 * NTILE;
     const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
-    // rows staged in LDS for batches of problems up to 32 centroids (measured
-    // faster there); one large problem reads its rows from F, with the loads
-    // of the next column steps in flight (1.6x faster at 1e6 x 96, k = 20)
-    const bool stage = NTILE <= 2 && b.count > 1 && stage_ok(F, ldf, b);
-    const size_t lds = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (stage ? (NT / 64) * 16 : 0)) * rp * sizeof(float);
+    // rows staged in LDS (16-byte loads) up to 32 centroids, measured faster
+    // there (1e6 x 96, k = 20: 0.24 -> 0.20 ms); with more centroids each lane
+    // reads its row from F, with the loads of the next column steps in flight
+    // (staging is 4% slower at k = 50, where the LDS of the staged rows costs
+    // resident blocks)
+    const size_t lds_staged = (size_t)2 * KC * sizeof(double) + (size_t)(KC + (NT / 64) * 16) * rp * sizeof(float);
+    const bool stage = NTILE <= 2 && stage_ok(F, ldf, b) && lds_staged <= 64 * 1024;
+    const size_t lds = stage ? lds_staged : (size_t)2 * KC * sizeof(double) + (size_t)KC * rp * sizeof(float);
     // many small problems: about 8 row groups per wavefront, so the centroid
     // staging of a block is spread over more rows
     const int64_t rows_per_block = (NT / 64) * 16 * (b.count > 1 ? 8 : 1);
@@ -967,12 +970,11 @@ void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float 
 
 void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
-    // matrix cores while the centroids (and, up to 32 centroids, 4 x 16 staged
-    // rows) fit 64 KB of LDS
+    // matrix cores while the centroids fit 64 KB of LDS (the rows are staged
+    // as well when they fit beside them)
     const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
     const int kc = ((k + 15) / 16) * 16;
-    const int staged = kc <= 32 && b.count > 1 && stage_ok(F, ldf, b) ? 64 : 0;
-    if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)(kc + staged) * rpad * 4 <= 64 * 1024) {
+    if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)kc * rpad * 4 <= 64 * 1024) {
         switch ((k + 15) / 16) {
             case 1: assign_mfma<1>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
             case 2: assign_mfma<2>(F, n, r, ldf, C, k, labels, dist2, dist64, b, s); return;
