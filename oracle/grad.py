@@ -59,8 +59,13 @@ def _operator(n, row_ptr, col_idx, w):
     return (sp.diags(s) - W).tocsr()
 
 
-def cheb_filter_adjoint(n, row_ptr, col_idx, w, lmax, a, R, G):
-    """(dw per stored entry, da) of <G, Y> with Y = sum_j a_j T_j(L~) R."""
+def cheb_filter_adjoint(n, row_ptr, col_idx, w, lmax, a, R, G, with_scale=False):
+    """(dw per stored entry, da) of <G, Y> with Y = sum_j a_j T_j(L~) R.
+
+    with_scale: also the per-entry sum over the steps of the absolute values of
+    the two terms each step adds to dw, (2/lmax) sum_j (|diag term| + |entry
+    term|), the scale on which rounding of those terms acts (dw itself can be
+    far smaller when they cancel)."""
     a = np.asarray(a, dtype=np.float64)
     p = len(a) - 1
     L = _operator(n, row_ptr, col_idx, w)
@@ -72,7 +77,8 @@ def cheb_filter_adjoint(n, row_ptr, col_idx, w, lmax, a, R, G):
     rows = np.repeat(np.arange(n), np.diff(np.asarray(row_ptr, dtype=np.int64)))
     cols = np.asarray(col_idx, dtype=np.int64)
     if p == 0:
-        return np.zeros(len(cols)), da
+        z = np.zeros(len(cols))
+        return (z, da, z.copy()) if with_scale else (z, da)
     # adjoints A_j for j = 1..p (A[j])
     A = [None] * (p + 2)
     A[p + 1] = np.zeros_like(G)
@@ -83,13 +89,20 @@ def cheb_filter_adjoint(n, row_ptr, col_idx, w, lmax, a, R, G):
     # M restricted to the stored pattern and the diagonal
     m_off = np.zeros(len(cols))
     m_diag = np.zeros(n)
+    absum = np.zeros(len(cols)) if with_scale else None
     for j in range(0, p):
         cj = 1.0 if j == 0 else 2.0
         Aj1 = A[j + 1]
         Tj = T[j]
-        m_off += cj * np.sum(Aj1[rows] * Tj[cols], axis=1)
-        m_diag += cj * np.sum(Aj1 * Tj, axis=1)
+        t_off = cj * np.sum(Aj1[rows] * Tj[cols], axis=1)
+        t_diag = cj * np.sum(Aj1 * Tj, axis=1)
+        m_off += t_off
+        m_diag += t_diag
+        if with_scale:
+            absum += np.abs(t_diag)[rows] + np.abs(t_off)
     dw = (2.0 / lmax) * (m_diag[rows] - m_off)
+    if with_scale:
+        return dw, da, (2.0 / lmax) * absum
     return dw, da
 
 
