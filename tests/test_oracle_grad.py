@@ -96,3 +96,24 @@ def test_sampled_adjoint_equals_full():
     dws, das = oracle.cheb_filter_adjoint_sampled(g.n, g.row_ptr, g.col_idx, w, lmax, a, R, G, ent)
     np.testing.assert_allclose(dws, dw[ent], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(das, da, rtol=1e-13)
+
+
+def test_adjoint_term_scale_bounds_the_gradient():
+    # the optional scale (sum over the steps of the two terms' absolute
+    # values) bounds |dw| entrywise by the triangle inequality, and asking
+    # for it leaves dw and da as they are
+    g = W.random_weighted(60, 0.15, 8, isolated=2)
+    w = g.w.astype(np.float64)
+    L = oracle.laplacian_sparse(g.n, g.row_ptr, g.col_idx, w)
+    lmax = 1.01 * oracle.lambda_max_exact(L)
+    a = oracle.cheb_coeffs(0.3 * lmax, lmax, 25)
+    _, R = W.signals(g.n, 4, 1)
+    G = W.signals_f64(g.n, 4, 2)
+    dw, da = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w, lmax, a, R, G)
+    dw2, da2, scale = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w, lmax, a, R, G, with_scale=True)
+    np.testing.assert_array_equal(dw, dw2)
+    np.testing.assert_array_equal(da, da2)
+    assert np.all(np.abs(dw) <= scale * (1 + 1e-12))
+    assert np.all(scale > 0)
+    z, _, zs = oracle.cheb_filter_adjoint(g.n, g.row_ptr, g.col_idx, w, lmax, a[:1], R, G, with_scale=True)
+    assert not np.any(z) and not np.any(zs)
