@@ -629,6 +629,52 @@ __global__ void update_partial_kernel(const float *__restrict__ F, int64_t n, in
     // 16 rows' labels and values loaded before they are added (clamped
     // in-range addresses, always issued: no load waits behind a branch)
     constexpr int U = 16;
+    if (r <= (int64_t)blockDim.x) {
+        // one column per thread: the next 16 rows' loads are issued before this
+        // group's additions, so they overlap (rows still added in order)
+        const int64_t col = threadIdx.x;
+        const bool colin = col < r;
+        const int64_t colc = colin ? col : 0;
+        int lab[U], labn[U];
+        float v[U], vn[U];
+        auto load = [&](int64_t ib, int *L, float *V) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = ib + u < i1;
+                const int64_t i = in ? ib + u : i1 - 1;
+                const int l = labels[i];
+                const float x = F[i * ldf + colc];
+                L[u] = in ? l : -1;
+                V[u] = (in && colin) ? x : 0.0f;
+            }
+        };
+        if (i0 < i1) load(i0, labn, vn);
+        for (int64_t ib = i0; ib < i1; ib += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                lab[u] = labn[u];
+                v[u] = vn[u];
+            }
+            if (ib + U < i1) load(ib + U, labn, vn);
+            if (colin) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = lab[u];
+                    if (c >= 0 && c < k) S[(int64_t)c * r + col] += (double)v[u];
+                }
+            }
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (lab[u] >= 0 && lab[u] < k) S[kr + lab[u]] += 1.0;
+            }
+        }
+        __syncthreads();
+        double *out = part + (int64_t)blockIdx.x * kr;
+        for (int64_t q = threadIdx.x; q < kr; q += blockDim.x) out[q] = S[q];
+        for (int q = threadIdx.x; q < k; q += blockDim.x) pcount[(int64_t)blockIdx.x * k + q] = (int64_t)S[kr + q];
+        return;
+    }
     for (int64_t ib = i0; ib < i1; ib += U) {
         int lab[U];
 #pragma unroll
