@@ -132,7 +132,7 @@ __device__ __forceinline__ void propose(float (&hd)[H], int (&hj)[H], float dv, 
 // them 16 at a time as the A operand (rows).  In the 16 x 16 x 4 MFMA output
 // lane l holds column l % 16 (its query) for rows 4 (l / 16) + v, v = 0..3: the
 // lane sees 4 candidates per tile and keeps its class's (l / 16) H nearest.
-template <int DS>
+template <int DS, bool VEC>
 __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict__ X, int64_t n, int d, int64_t ldx,
                                                          const float *__restrict__ nrm, float *__restrict__ cand_d,
                                                          int32_t *__restrict__ cand_j) {
@@ -167,10 +167,40 @@ __global__ __launch_bounds__(NT) void knn_propose_kernel(const float *__restrict
     }
     for (int64_t c0 = 0; c0 < n; c0 += CB) {
         __syncthreads();
-        for (int q = threadIdx.x; q < CB * 4 * DS; q += NT) {
-            const int p = q / (4 * DS), c = q - p * (4 * DS);
-            const int64_t j = c0 + p;
-            xs[p * DP + c] = (j < n && c < d) ? X[j * ldx + c] : 0.0f;
+        if constexpr (VEC) {
+            // rows of 16-byte quads: four 16-byte loads per thread in flight
+            // (clamped in-range addresses, always issued), then their LDS
+            // stores; zero past d and past n
+            const int64_t ldq = ldx >> 2;
+            const v4f *X4 = reinterpret_cast<const v4f *>(X);
+            for (int e0 = 0; e0 < CB * DS; e0 += 4 * NT) {
+                v4f v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * NT + threadIdx.x;
+                    const int p = e / DS, cq = e - p * DS;
+                    const int64_t j = c0 + p;
+                    // quads at or past d are not read (DS may exceed ceil(d / 4))
+                    const bool in = e < CB * DS && j < n && 4 * cq < d;
+                    const v4f x = X4[in ? j * ldq + cq : 0];
+                    v[u] = in ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * NT + threadIdx.x;
+                    if (e < CB * DS) {
+                        const int p = e / DS, cq = e - p * DS;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) xs[p * DP + 4 * cq + k] = 4 * cq + k < d ? v[u][k] : 0.0f;
+                    }
+                }
+            }
+        } else {
+            for (int q = threadIdx.x; q < CB * 4 * DS; q += NT) {
+                const int p = q / (4 * DS), c = q - p * (4 * DS);
+                const int64_t j = c0 + p;
+                xs[p * DP + c] = (j < n && c < d) ? X[j * ldx + c] : 0.0f;
+            }
         }
         // rows past n: +inf norm, so their distances are +inf and never proposed
         for (int p = threadIdx.x; p < CB; p += NT) ns[p] = (c0 + p < n) ? nrm[c0 + p] : __builtin_inff();
@@ -475,7 +505,10 @@ __global__ void union_fill_kernel(const float *__restrict__ X, int64_t ldx, int 
 template <int DS>
 void launch_propose(const float *X, int64_t n, int d, int64_t ldx, const KnnWs &w, hipStream_t s) {
     const unsigned grid = (unsigned)((n + QB - 1) / QB);
-    knn_propose_kernel<DS><<<grid, NT, 0, s>>>(X, n, d, ldx, w.nrm, w.cand_d, w.cand_j);
+    if (aligned(X, 16) && ldx % 4 == 0)
+        knn_propose_kernel<DS, true><<<grid, NT, 0, s>>>(X, n, d, ldx, w.nrm, w.cand_d, w.cand_j);
+    else
+        knn_propose_kernel<DS, false><<<grid, NT, 0, s>>>(X, n, d, ldx, w.nrm, w.cand_d, w.cand_j);
 }
 
 void scan_i32(const int32_t *in, int64_t n, int64_t *tile_sums, int64_t *out, hipStream_t s) {

@@ -14,8 +14,13 @@ from gpu_util import host, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _check(X, K, ref=None):
-    out = asc.knn_graph(to_dev(X.astype(np.float32)), K)
+def _check(X, K, ref=None, ld=None):
+    Xd = to_dev(X.astype(np.float32))
+    if ld is not None:  # rows ld floats apart (columns past d hold other values)
+        buf = to_dev(np.full((len(X), ld), 7.5, np.float32))
+        buf[:, :X.shape[1]] = Xd
+        Xd = buf[:, :X.shape[1]]
+    out = asc.knn_graph(Xd, K)
     idx, d2 = ref if ref is not None else oknn.knn_bruteforce(X, K)
     np.testing.assert_array_equal(host(out["nbr"]), idx)
     np.testing.assert_array_equal(host(out["nbr_d2"]), d2)
@@ -27,7 +32,7 @@ def _check(X, K, ref=None):
 
 
 @pytest.mark.parametrize("n,d,K", [(300, 3, 6), (1000, 16, 10), (777, 5, 1), (513, 17, 32), (129, 64, 7),
-                                   (2000, 2, 9), (40, 1, 3), (33, 33, 32)])
+                                   (2000, 2, 9), (40, 1, 3), (33, 33, 32), (1000, 20, 10), (700, 8, 5)])
 def test_knn_matches_oracle(n, d, K):
     rng = np.random.default_rng(n + d + K)
     if d <= 3:
@@ -82,3 +87,11 @@ def test_knn_full_size_gaussian_mixture_and_weights():
     w = asc.gauss_weights(out["d2"], 2.0)
     rp, ci, dd = oknn.union_graph(len(X), ref[0], X)
     np.testing.assert_allclose(host(w), oracle.gauss_weights(dd.astype(np.float64), 2.0), rtol=1e-7)
+
+
+@pytest.mark.parametrize("d,ld", [(18, 20), (18, 24), (13, 16), (16, 20)])
+def test_knn_rows_with_a_wider_leading_dimension(d, ld):
+    # 16-byte rows with padding past d (the padding holds other values, which
+    # must not reach the distances), and quads past d never read
+    X = np.random.default_rng(d * ld).standard_normal((900, d)).astype(np.float32) * 2.0
+    _check(X, 9, ld=ld)
