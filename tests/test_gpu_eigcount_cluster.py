@@ -117,7 +117,7 @@ def test_kmeans_assign_bit_exact(n, r, k):
     np.testing.assert_array_equal(host(labels_nd), lab_ref)
 
 
-@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (20000, 96, 50), (100, 8, 7)])
+@pytest.mark.parametrize("n,r,k", [(5000, 64, 20), (20000, 96, 50), (100, 8, 7), (3000, 300, 10), (2000, 40, 3)])
 def test_kmeans_update_matches_oracle(n, r, k):
     rng = np.random.default_rng(k)
     F = rng.standard_normal((n, r)).astype(np.float32)
