@@ -220,33 +220,43 @@ __global__ __launch_bounds__(NT) void stab_combine_all_kernel(int64_t n, int rs,
     }
 }
 
-// one block per realisation: inertia of every replicate (float64, fixed
-// order), the least one (lowest replicate on ties) gives the labels
-__global__ __launch_bounds__(NT) void select_kernel(const double *__restrict__ dist64,
+// one block per (realisation, replicate): its inertia, the float64 sum of the
+// rows' least distances (each thread's rows in order, then the fixed block sum)
+__global__ __launch_bounds__(NT) void inertia_kernel(const double *__restrict__ dist64, int64_t n,
+                                                     double *__restrict__ inert) {
+    __shared__ double lds[NT / 64];
+    const int64_t jr = blockIdx.x;
+    const double *d = dist64 + jr * n;
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < n; i += NT) v[0] += d[i];
+    block_sum<1, NT>(v, lds);
+    if (threadIdx.x == 0) inert[jr] = v[0];
+}
+
+// per realisation (blockIdx.y): the replicate of least inertia, the lowest one
+// on ties, gives the labels; blocks along x share the copy
+__global__ __launch_bounds__(NT) void select_kernel(const double *__restrict__ inert,
                                                     const int32_t *__restrict__ lab_all, int64_t n, int reps,
                                                     int32_t *__restrict__ lab_out, double *__restrict__ inertia) {
-    __shared__ double lds[NT / 64];
     __shared__ int best;
-    const int j = blockIdx.x;
-    double best_v = 0.0;
-    int best_r = 0;
-    for (int rep = 0; rep < reps; ++rep) {
-        const double *d = dist64 + ((int64_t)j * reps + rep) * n;
-        double v[1] = {0.0};
-        for (int64_t i = threadIdx.x; i < n; i += NT) v[0] += d[i];
-        block_sum<1, NT>(v, lds);
-        if (threadIdx.x == 0) {
-            if (inertia) inertia[(int64_t)j * reps + rep] = v[0];
-            if (rep == 0 || v[0] < best_v) {
-                best_v = v[0];
+    const int j = blockIdx.y;
+    const double *v = inert + (int64_t)j * reps;
+    if (threadIdx.x == 0) {
+        double best_v = v[0];
+        int best_r = 0;
+        for (int rep = 1; rep < reps; ++rep)
+            if (v[rep] < best_v) {
+                best_v = v[rep];
                 best_r = rep;
             }
-        }
+        best = best_r;
     }
-    if (threadIdx.x == 0) best = best_r;
+    if (inertia && blockIdx.x == 0)
+        for (int rep = threadIdx.x; rep < reps; rep += NT) inertia[(int64_t)j * reps + rep] = v[rep];
     __syncthreads();
     const int32_t *src = lab_all + ((int64_t)j * reps + best) * n;
-    for (int64_t i = threadIdx.x; i < n; i += NT) lab_out[(int64_t)j * n + i] = src[i];
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        lab_out[(int64_t)j * n + i] = src[i];
 }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
@@ -368,6 +378,7 @@ struct StabWs {
     float *C;
     int32_t *lab_all;
     double *dist64;
+    double *inert;  // per (realisation, replicate) inertia
     void *kmws;
     double *ari;
     int32_t *labels;
@@ -404,6 +415,7 @@ size_t stab_ws_layout(const asc_graph *g, const StabDims &d, asc_dtype sig, void
     w.C = a.take<float>((size_t)d.J * d.reps * d.kmax * d.etamax_used);
     w.lab_all = a.take<int32_t>((size_t)d.J * d.reps * n);
     w.dist64 = a.take<double>((size_t)d.J * d.reps * n);
+    w.inert = a.take<double>((size_t)d.J * d.reps);
     w.kmws = a.take<char>(km_update_ws(n, d.etamax_used, d.kmax, d.J * d.reps));
     w.ari = a.take<double>((size_t)npairs);
     w.labels = a.take<int32_t>((size_t)d.J * n);
@@ -595,8 +607,10 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, w.dist64, b, s);
         ASC_LAUNCHED();
         int32_t *lab_k = labels ? labels + (int64_t)kk * J * n : w.labels;
-        select_kernel<<<J, NT, 0, s>>>(w.dist64, w.lab_all, n, reps, lab_k,
-                                       inertia ? inertia + (int64_t)kk * J * reps : nullptr);
+        inertia_kernel<<<(unsigned)(J * reps), NT, 0, s>>>(w.dist64, n, w.inert);
+        ASC_LAUNCHED();
+        select_kernel<<<dim3((unsigned)std::min<int64_t>((n + NT - 1) / NT, 64), (unsigned)J), NT, 0, s>>>(
+            w.inert, w.lab_all, n, reps, lab_k, inertia ? inertia + (int64_t)kk * J * reps : nullptr);
         ASC_LAUNCHED();
         double *ari_k = ari ? ari + (int64_t)kk * npairs : w.ari;
         ari_kernel<<<npairs, NT, ari_lds(k), s>>>(lab_k, n, n, J, k, ari_k, &w.hdr->flags);
