@@ -12,6 +12,11 @@ namespace asc {
 // count problems, problem b reads feature block b / fdiv (fstride elements
 // apart) and owns centroids b (cstride), labels/distances b (lstride) and
 // initial rows b (rows_stride).  The default is one problem.
+// stamp (optional, count values): problem b is skipped by km_assign and
+// km_update (its labels and centroids left as they are) while stamp[b] <
+// want, and km_assign sets stamp[b] = mark (when mark != 0) if it changes a
+// label of problem b.  With marks that only grow, a launch's blocks all see a
+// problem the same way: a problem that runs can only be raised past want.
 struct KmBatch {
     int count = 1;
     int64_t fstride = 0;
@@ -19,6 +24,9 @@ struct KmBatch {
     int64_t cstride = 0;
     int64_t lstride = 0;
     int64_t rows_stride = 0;
+    uint32_t *stamp = nullptr;
+    uint32_t want = 0;
+    uint32_t mark = 0;
 };
 
 void km_normalize(float *Y, int64_t n, int64_t r, int64_t ldy, float *norms, hipStream_t s);

@@ -350,6 +350,11 @@ __global__ __launch_bounds__(NT) void ari_kernel(const int32_t *__restrict__ lab
 
 __global__ void clear_flags_kernel(uint32_t *flags) { flags[0] = 0u; }
 
+__global__ void zero_u32_kernel(uint32_t *v, int64_t m) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x)
+        v[q] = 0u;
+}
+
 // dynamic LDS of ari_kernel: the k x k table, at least the 4 x (NT/64) wavefront sums it later holds
 size_t ari_lds(int k) {
     return std::max<size_t>((size_t)k * k * sizeof(int), 4 * (NT / 64) * sizeof(long long));
@@ -379,6 +384,7 @@ struct StabWs {
     int32_t *lab_all;
     double *dist64;
     double *inert;  // per (realisation, replicate) inertia
+    uint32_t *stamp;  // per (realisation, replicate): the last Lloyd step that moved a label
     void *kmws;
     double *ari;
     int32_t *labels;
@@ -416,6 +422,7 @@ size_t stab_ws_layout(const asc_graph *g, const StabDims &d, asc_dtype sig, void
     w.lab_all = a.take<int32_t>((size_t)d.J * d.reps * n);
     w.dist64 = a.take<double>((size_t)d.J * d.reps * n);
     w.inert = a.take<double>((size_t)d.J * d.reps);
+    w.stamp = a.take<uint32_t>((size_t)d.J * d.reps);
     w.kmws = a.take<char>(km_update_ws(n, d.etamax_used, d.kmax, d.J * d.reps));
     w.ari = a.take<double>((size_t)npairs);
     w.labels = a.take<int32_t>((size_t)d.J * n);
@@ -575,6 +582,9 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         ASC_LAUNCHED();
     }
     // 4. per k: (features,) normalisation, batched k-means, selection, ARIs
+    zero_u32_kernel<<<(unsigned)std::min<int64_t>(((int64_t)J * reps + NT - 1) / NT, 256), NT, 0, s>>>(
+        w.stamp, (int64_t)J * reps);
+    ASC_LAUNCHED();
     for (int kk = 0; kk < d.nk; ++kk) {
         const int k = k_min + kk;
         const int eta = eta_host[kk];
@@ -598,10 +608,27 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         const int32_t *rows_k = init_rows + (int64_t)kk * J * reps * k_max;
         km_init_rows(Yk, n, eta, ld, rows_k, k, w.C, b, s);
         ASC_LAUNCHED();
+        // Lloyd's steps stop per problem at a fixed point: once an assignment
+        // leaves every label of a problem as it was, its update would return
+        // the centroids it already has (the same member sums in the same
+        // order; an empty cluster keeps its centroid) and every later step
+        // would repeat itself, so those steps are skipped, which leaves the
+        // labels and centroids bit for bit as if they had run.  Assignment it
+        // (it >= 1) stamps base + it + 1 on a problem whose labels it
+        // changes; the update of step it runs only with that stamp, and the
+        // assignment of step it + 1 only with the stamp of step it.  Stamps
+        // grow over the whole sweep (base rises per k), so an older k's
+        // stamps never let a problem run.
+        const uint32_t base = (uint32_t)kk * (uint32_t)(kmeans_iters + 1);
         for (int it = 0; it < kmeans_iters; ++it) {
-            km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, nullptr, b, s);
+            KmBatch ba = b, bu = b;
+            ba.stamp = bu.stamp = w.stamp;
+            ba.want = it >= 2 ? base + (uint32_t)it : 0u;
+            ba.mark = it >= 1 ? base + (uint32_t)it + 1u : 0u;
+            bu.want = it >= 1 ? base + (uint32_t)it + 1u : 0u;
+            km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, nullptr, ba, s);
             ASC_LAUNCHED();
-            km_update(Yk, n, eta, ld, w.lab_all, k, w.C, nullptr, w.kmws, b, s);
+            km_update(Yk, n, eta, ld, w.lab_all, k, w.C, nullptr, w.kmws, bu, s);
             ASC_LAUNCHED();
         }
         km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, w.dist64, b, s);
