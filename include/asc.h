@@ -253,6 +253,25 @@ asc_status asc_kmeanspp(const float *F, int64_t n, int64_t r, int64_t ldf, int k
 asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *labels, int k,
                              float *C, int64_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* k-means with replicates (Sec. 5 clusters with Matlab's k-means and 20
+ * replicates): reps independent runs of Lloyd's method over the same F, run q
+ * starting from C = F[rows[q*k + c]] (rows[reps*k], int32 on the device; an
+ * out-of-range row reads row 0), each taking iters steps of
+ * asc_kmeans_assign then asc_kmeans_update (same arithmetic, same results)
+ * and a last assignment.  A run's inertia is sum_i min_c d(i, c), the
+ * float64 distances of that assignment summed in a fixed order; the run of
+ * least inertia (the lowest q on ties) gives labels[n] (int32) and, when C is
+ * not NULL, its centroids C[k*r] (float32).  inertia[reps] (float64, may be
+ * NULL) receives every run's inertia.  A run whose assignment changes no
+ * label has reached a fixed point: its remaining steps are skipped, which
+ * changes no result.  F: n x r float32 (ldf); 1 <= k <= 1024, 1 <= reps <=
+ * 65535, 0 <= iters <= 10000.  ws: asc_kmeans_replicates_workspace(n, r, k,
+ * reps) bytes (0 for invalid sizes). */
+size_t asc_kmeans_replicates_workspace(int64_t n, int64_t r, int k, int reps);
+asc_status asc_kmeans_replicates(const float *F, int64_t n, int64_t r, int64_t ldf, int k, int reps, int iters,
+                                 const int32_t *rows, int32_t *labels, float *C, double *inertia, void *ws,
+                                 size_t ws_bytes, void *stream);
+
 /* ---- differentiation (extension beyond the paper) ----
  * Conventions: lambda_max is a constant; every stored CSR entry e = (i,k) is
  * its own parameter w_e, entering L as L_ik = -w_e and L_ii = sum_e w_e, so

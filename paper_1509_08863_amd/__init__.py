@@ -18,7 +18,7 @@ from ._abi import AscError, ASC_F32, ASC_BF16  # noqa: F401
 
 __all__ = ["Graph", "graph_prepare", "lmax_estimate", "cheb_coeffs", "cheb_filter", "cheb_moments",
            "eigcount_dichotomy", "eigcount_lambda_k", "normalize_features", "kmeans_init_rows",
-           "kmeans_assign", "kmeans_update", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
+           "kmeans_assign", "kmeans_update", "kmeans_replicates", "read_flags", "workspace", "AscError", "tune_set", "tune_get",
            "tune_save", "tune_load", "autotune_filter", "cheb_filter_bwd", "gauss_weights", "gauss_weights_bwd",
            "rownorm_loss_bwd", "Batch", "stream_copy",
            "lambda_k_filter", "cheb_filter_noalloc"]
@@ -309,6 +309,24 @@ def kmeans_update(F: torch.Tensor, labels: torch.Tensor, C: torch.Tensor, ws: to
     _abi.check(L.asc_kmeans_update(_ptr(F), n, r, _ld(F), _ptr(labels), k, _ptr(C), _ptr(counts), _ptr(ws),
                                    ws.numel(), _stream()))
     return counts
+
+
+def kmeans_replicates(F: torch.Tensor, rows: torch.Tensor, iters: int):
+    """Lloyd's method from each row of `rows` (reps x k tensor of initial rows
+    of F), iters steps each; returns (labels, C, inertia): the labels and
+    centroids of the run of least inertia and every run's inertia (float64)."""
+    L = _abi.lib()
+    n, r = F.shape
+    reps, k = rows.shape
+    rows = rows.to(device=F.device, dtype=torch.int32).contiguous()
+    labels = torch.empty(n, dtype=torch.int32, device=F.device)
+    C = torch.empty(k, r, dtype=torch.float32, device=F.device)
+    inertia = torch.empty(reps, dtype=torch.float64, device=F.device)
+    ws = workspace(L.asc_kmeans_replicates_workspace(n, r, k, reps), F.device)
+    _abi.check(L.asc_kmeans_replicates(_ptr(F), n, r, _ld(F), k, reps, iters, _ptr(rows), _ptr(labels), _ptr(C),
+                                       _ptr(inertia), _ptr(ws), ws.numel(), _stream()))
+    kmeans_replicates.last_ws = ws
+    return labels, C, inertia
 
 
 def read_flags(ws: torch.Tensor, raise_on_error: bool = True) -> int:

@@ -72,6 +72,8 @@ SIGNATURES = {
     "asc_kmeanspp_workspace": (SZ, [I64]),
     "asc_kmeanspp": (I32, [P, I64, I64, I64, I32, P, P, P, SZ, P]),
     "asc_kmeans_update": (I32, [P, I64, I64, I64, P, I32, P, P, P, SZ, P]),
+    "asc_kmeans_replicates_workspace": (SZ, [I64, I64, I32, I32]),
+    "asc_kmeans_replicates": (I32, [P, I64, I64, I64, I32, I32, I32, P, P, P, P, P, SZ, P]),
     "asc_stream_copy": (I32, [P, P, SZ, P]),
     "asc_gather_probe": (I32, [P, I64, P, I64, P, P]),
     "asc_read_flags": (I32, [P, ctypes.POINTER(ctypes.c_uint32), P]),

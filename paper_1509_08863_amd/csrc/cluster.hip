@@ -960,6 +960,57 @@ __global__ __launch_bounds__(256) void update_final_lanes_kernel(int nblocks, in
     }
 }
 
+// one block per problem: its inertia, the float64 sum of the rows' least
+// distances (each thread's rows in order, then the fixed block sum)
+__global__ __launch_bounds__(NT) void inertia_kernel(const double *__restrict__ dist64, int64_t n,
+                                                     double *__restrict__ inert) {
+    __shared__ double lds[NT / 64];
+    const int64_t q = blockIdx.x;
+    const double *d = dist64 + q * n;
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < n; i += NT) v[0] += d[i];
+    block_sum<1, NT>(v, lds);
+    if (threadIdx.x == 0) inert[q] = v[0];
+}
+
+// per group of reps problems (blockIdx.y): the problem of least inertia, the
+// lowest one on ties, gives the labels (and centroids, when asked); blocks
+// along x share the copy
+__global__ __launch_bounds__(NT) void select_kernel(const double *__restrict__ inert,
+                                                    const int32_t *__restrict__ lab_all, int64_t n, int reps,
+                                                    int32_t *__restrict__ lab_out, double *__restrict__ inertia,
+                                                    const float *__restrict__ C_all, int64_t ckr,
+                                                    float *__restrict__ C_out) {
+    __shared__ int best;
+    const int j = blockIdx.y;
+    const double *v = inert + (int64_t)j * reps;
+    if (threadIdx.x == 0) {
+        double best_v = v[0];
+        int best_r = 0;
+        for (int rep = 1; rep < reps; ++rep)
+            if (v[rep] < best_v) {
+                best_v = v[rep];
+                best_r = rep;
+            }
+        best = best_r;
+    }
+    if (inertia && blockIdx.x == 0)
+        for (int rep = threadIdx.x; rep < reps; rep += NT) inertia[(int64_t)j * reps + rep] = v[rep];
+    __syncthreads();
+    const int32_t *src = lab_all + ((int64_t)j * reps + best) * n;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        lab_out[(int64_t)j * n + i] = src[i];
+    if (C_out && blockIdx.x == 0) {
+        const float *cs = C_all + ((int64_t)j * reps + best) * ckr;
+        for (int64_t q = threadIdx.x; q < ckr; q += NT) C_out[(int64_t)j * ckr + q] = cs[q];
+    }
+}
+
+__global__ void zero_u32_kernel(uint32_t *v, int64_t m) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x)
+        v[q] = 0u;
+}
+
 int update_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
 
 asc_status check_feat(const float *F, int64_t n, int64_t r, int64_t ldf, const char *who) {
@@ -1134,6 +1185,41 @@ void km_update(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t 
     update_final_kernel<<<g2, 256, 0, s>>>(nb, r, k, part, pcount, C, counts, to_bat(b));
 }
 
+void km_zero_stamps(uint32_t *stamp, int64_t count, hipStream_t s) {
+    zero_u32_kernel<<<(unsigned)std::min<int64_t>((count + NT - 1) / NT, 256), NT, 0, s>>>(stamp, count);
+}
+
+// Lloyd's steps stop per problem at a fixed point: once an assignment leaves
+// every label of a problem as it was, its update would return the centroids
+// it already has (the same member sums in the same order; an empty cluster
+// keeps its centroid) and every later step would repeat itself, so those
+// steps are skipped, which leaves the labels and centroids bit for bit as if
+// they had run.  Assignment it (it >= 1) stamps base + it + 1 on a problem
+// whose labels it changes; the update of step it runs only with that stamp,
+// and the assignment of step it + 1 only with the stamp of step it.
+void km_lloyd(const float *F, int64_t n, int64_t r, int64_t ldf, const int32_t *rows, int k, int iters, float *C,
+              int32_t *labels, double *dist64, void *ws, uint32_t *stamp, uint32_t base, const KmBatch &b,
+              hipStream_t s) {
+    km_init_rows(F, n, r, ldf, rows, k, C, b, s);
+    for (int it = 0; it < iters; ++it) {
+        KmBatch ba = b, bu = b;
+        ba.stamp = bu.stamp = stamp;
+        ba.want = it >= 2 ? base + (uint32_t)it : 0u;
+        ba.mark = it >= 1 ? base + (uint32_t)it + 1u : 0u;
+        bu.want = it >= 1 ? base + (uint32_t)it + 1u : 0u;
+        km_assign(F, n, r, ldf, C, k, labels, nullptr, nullptr, ba, s);
+        km_update(F, n, r, ldf, labels, k, C, nullptr, ws, bu, s);
+    }
+    km_assign(F, n, r, ldf, C, k, labels, nullptr, dist64, b, s);
+}
+
+void km_select(const double *dist64, const int32_t *lab_all, int64_t n, int groups, int reps, double *inert,
+               int32_t *lab_out, double *inertia_out, const float *C_all, int64_t ckr, float *C_out, hipStream_t s) {
+    inertia_kernel<<<(unsigned)(groups * reps), NT, 0, s>>>(dist64, n, inert);
+    select_kernel<<<dim3((unsigned)std::min<int64_t>((n + NT - 1) / NT, 64), (unsigned)groups), NT, 0, s>>>(
+        inert, lab_all, n, reps, lab_out, inertia_out, C_all, ckr, C_out);
+}
+
 }  // namespace asc
 
 using namespace asc;
@@ -1180,6 +1266,66 @@ extern "C" asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, in
         return fail(ASC_ERR_INVALID, "%s: bad arguments", who);
     ASC_TRY(check_ws(ws, ws_bytes, asc_kmeans_update_workspace(n, r, k), who));
     km_update(F, n, r, ldf, labels, k, C, counts, ws, KmBatch{}, as_stream(stream));
+    ASC_LAUNCHED();
+    return ASC_OK;
+}
+
+static KmBatch replicate_batch(int64_t n, int64_t r, int k, int reps) {
+    KmBatch b;
+    b.count = reps;
+    b.fstride = 0;  // every replicate reads the same rows
+    b.cstride = (int64_t)k * r;
+    b.lstride = n;
+    b.rows_stride = k;
+    return b;
+}
+
+struct RepWs {
+    float *C;
+    int32_t *lab;
+    double *dist64;
+    double *inert;
+    uint32_t *stamp;
+    void *kmws;
+};
+
+static size_t replicates_layout(int64_t n, int64_t r, int k, int reps, void *ws, RepWs *out) {
+    Arena a(ws);
+    RepWs w;
+    w.C = a.take<float>((size_t)reps * k * r);
+    w.lab = a.take<int32_t>((size_t)reps * n);
+    w.dist64 = a.take<double>((size_t)reps * n);
+    w.inert = a.take<double>((size_t)reps);
+    w.stamp = a.take<uint32_t>((size_t)reps);
+    w.kmws = a.take<char>(km_update_ws(n, r, k, reps));
+    if (out) *out = w;
+    return a.size();
+}
+
+extern "C" size_t asc_kmeans_replicates_workspace(int64_t n, int64_t r, int k, int reps) {
+    if (n < 1 || r < 1 || k < 1 || reps < 1) return 0;
+    return replicates_layout(n, r, k, reps, nullptr, nullptr);
+}
+
+extern "C" asc_status asc_kmeans_replicates(const float *F, int64_t n, int64_t r, int64_t ldf, int k, int reps,
+                                            int iters, const int32_t *rows, int32_t *labels, float *C,
+                                            double *inertia, void *ws, size_t ws_bytes, void *stream) {
+    const char *who = "asc_kmeans_replicates";
+    ASC_TRY(check_feat(F, n, r, ldf, who));
+    if (k < 1 || k > 1024) return fail(ASC_ERR_INVALID, "%s: k=%d not in [1, 1024]", who, k);
+    if (reps < 1 || reps > 65535) return fail(ASC_ERR_INVALID, "%s: reps=%d not in [1, 65535]", who, reps);
+    if (iters < 0 || iters > 10000) return fail(ASC_ERR_INVALID, "%s: iters=%d not in [0, 10000]", who, iters);
+    if (!rows || !labels || !aligned(rows, 4) || !aligned(labels, 4) || (C && !aligned(C, 4)) ||
+        (inertia && !aligned(inertia, 8)))
+        return fail(ASC_ERR_INVALID, "%s: rows/labels NULL or an argument misaligned", who);
+    ASC_TRY(check_ws(ws, ws_bytes, asc_kmeans_replicates_workspace(n, r, k, reps), who));
+    hipStream_t s = as_stream(stream);
+    RepWs w;
+    replicates_layout(n, r, k, reps, ws, &w);
+    const KmBatch b = replicate_batch(n, r, k, reps);
+    km_zero_stamps(w.stamp, reps, s);
+    km_lloyd(F, n, r, ldf, rows, k, iters, w.C, w.lab, w.dist64, w.kmws, w.stamp, 0u, b, s);
+    km_select(w.dist64, w.lab, n, 1, reps, w.inert, labels, inertia, w.C, (int64_t)k * r, C, s);
     ASC_LAUNCHED();
     return ASC_OK;
 }

@@ -220,45 +220,6 @@ __global__ __launch_bounds__(NT) void stab_combine_all_kernel(int64_t n, int rs,
     }
 }
 
-// one block per (realisation, replicate): its inertia, the float64 sum of the
-// rows' least distances (each thread's rows in order, then the fixed block sum)
-__global__ __launch_bounds__(NT) void inertia_kernel(const double *__restrict__ dist64, int64_t n,
-                                                     double *__restrict__ inert) {
-    __shared__ double lds[NT / 64];
-    const int64_t jr = blockIdx.x;
-    const double *d = dist64 + jr * n;
-    double v[1] = {0.0};
-    for (int64_t i = threadIdx.x; i < n; i += NT) v[0] += d[i];
-    block_sum<1, NT>(v, lds);
-    if (threadIdx.x == 0) inert[jr] = v[0];
-}
-
-// per realisation (blockIdx.y): the replicate of least inertia, the lowest one
-// on ties, gives the labels; blocks along x share the copy
-__global__ __launch_bounds__(NT) void select_kernel(const double *__restrict__ inert,
-                                                    const int32_t *__restrict__ lab_all, int64_t n, int reps,
-                                                    int32_t *__restrict__ lab_out, double *__restrict__ inertia) {
-    __shared__ int best;
-    const int j = blockIdx.y;
-    const double *v = inert + (int64_t)j * reps;
-    if (threadIdx.x == 0) {
-        double best_v = v[0];
-        int best_r = 0;
-        for (int rep = 1; rep < reps; ++rep)
-            if (v[rep] < best_v) {
-                best_v = v[rep];
-                best_r = rep;
-            }
-        best = best_r;
-    }
-    if (inertia && blockIdx.x == 0)
-        for (int rep = threadIdx.x; rep < reps; rep += NT) inertia[(int64_t)j * reps + rep] = v[rep];
-    __syncthreads();
-    const int32_t *src = lab_all + ((int64_t)j * reps + best) * n;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-        lab_out[(int64_t)j * n + i] = src[i];
-}
-
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -349,11 +310,6 @@ __global__ __launch_bounds__(NT) void ari_kernel(const int32_t *__restrict__ lab
 }
 
 __global__ void clear_flags_kernel(uint32_t *flags) { flags[0] = 0u; }
-
-__global__ void zero_u32_kernel(uint32_t *v, int64_t m) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x)
-        v[q] = 0u;
-}
 
 // dynamic LDS of ari_kernel: the k x k table, at least the 4 x (NT/64) wavefront sums it later holds
 size_t ari_lds(int k) {
@@ -582,8 +538,7 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         ASC_LAUNCHED();
     }
     // 4. per k: (features,) normalisation, batched k-means, selection, ARIs
-    zero_u32_kernel<<<(unsigned)std::min<int64_t>(((int64_t)J * reps + NT - 1) / NT, 256), NT, 0, s>>>(
-        w.stamp, (int64_t)J * reps);
+    km_zero_stamps(w.stamp, J * reps, s);
     ASC_LAUNCHED();
     for (int kk = 0; kk < d.nk; ++kk) {
         const int k = k_min + kk;
@@ -606,38 +561,14 @@ extern "C" asc_status asc_stability(const asc_graph *g, const double *lmax, int 
         b.lstride = n;
         b.rows_stride = k_max;
         const int32_t *rows_k = init_rows + (int64_t)kk * J * reps * k_max;
-        km_init_rows(Yk, n, eta, ld, rows_k, k, w.C, b, s);
-        ASC_LAUNCHED();
-        // Lloyd's steps stop per problem at a fixed point: once an assignment
-        // leaves every label of a problem as it was, its update would return
-        // the centroids it already has (the same member sums in the same
-        // order; an empty cluster keeps its centroid) and every later step
-        // would repeat itself, so those steps are skipped, which leaves the
-        // labels and centroids bit for bit as if they had run.  Assignment it
-        // (it >= 1) stamps base + it + 1 on a problem whose labels it
-        // changes; the update of step it runs only with that stamp, and the
-        // assignment of step it + 1 only with the stamp of step it.  Stamps
-        // grow over the whole sweep (base rises per k), so an older k's
-        // stamps never let a problem run.
-        const uint32_t base = (uint32_t)kk * (uint32_t)(kmeans_iters + 1);
-        for (int it = 0; it < kmeans_iters; ++it) {
-            KmBatch ba = b, bu = b;
-            ba.stamp = bu.stamp = w.stamp;
-            ba.want = it >= 2 ? base + (uint32_t)it : 0u;
-            ba.mark = it >= 1 ? base + (uint32_t)it + 1u : 0u;
-            bu.want = it >= 1 ? base + (uint32_t)it + 1u : 0u;
-            km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, nullptr, ba, s);
-            ASC_LAUNCHED();
-            km_update(Yk, n, eta, ld, w.lab_all, k, w.C, nullptr, w.kmws, bu, s);
-            ASC_LAUNCHED();
-        }
-        km_assign(Yk, n, eta, ld, w.C, k, w.lab_all, nullptr, w.dist64, b, s);
+        // stamps grow over the whole sweep (base rises per k), so an older
+        // k's stamps never let a problem run
+        km_lloyd(Yk, n, eta, ld, rows_k, k, kmeans_iters, w.C, w.lab_all, w.dist64, w.kmws, w.stamp,
+                 (uint32_t)kk * (uint32_t)(kmeans_iters + 1), b, s);
         ASC_LAUNCHED();
         int32_t *lab_k = labels ? labels + (int64_t)kk * J * n : w.labels;
-        inertia_kernel<<<(unsigned)(J * reps), NT, 0, s>>>(w.dist64, n, w.inert);
-        ASC_LAUNCHED();
-        select_kernel<<<dim3((unsigned)std::min<int64_t>((n + NT - 1) / NT, 64), (unsigned)J), NT, 0, s>>>(
-            w.inert, w.lab_all, n, reps, lab_k, inertia ? inertia + (int64_t)kk * J * reps : nullptr);
+        km_select(w.dist64, w.lab_all, n, J, reps, w.inert, lab_k, inertia ? inertia + (int64_t)kk * J * reps : nullptr,
+                  nullptr, 0, nullptr, s);
         ASC_LAUNCHED();
         double *ari_k = ari ? ari + (int64_t)kk * npairs : w.ari;
         ari_kernel<<<npairs, NT, ari_lds(k), s>>>(lab_k, n, n, J, k, ari_k, &w.hdr->flags);
