@@ -281,7 +281,13 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
     typedef float v4f __attribute__((ext_vector_type(4)));
     constexpr int KC = 16 * NTILE;
     extern __shared__ double lds_d[];
-    const int RP = (int)((r + 3) & ~int64_t(3)) + 1;      // odd stride: fewer bank conflicts
+    // row stride RP = 2 (mod 4): the 32 lanes of a half-wavefront, (li, lk)
+    // with li < 16 and lk < 2, read li * RP + lk + const, and 2 li (RP / 2)
+    // takes every even bank once as li runs over 16 rows (RP / 2 odd), so the
+    // matrix-core operand reads are free of bank conflicts (with an odd
+    // stride, conflicts took 7-12% of the cycles, now 1.5-3%; the time is
+    // the same, the kernel being bound by vector issue)
+    const int RP = (int)((r + 3) & ~int64_t(3)) + 2;
     double *cn = lds_d;                                   // |c|^2, KC values
     double *cs = lds_d + KC;                              // |c|, KC values
     float *Cs = reinterpret_cast<float *>(lds_d + 2 * KC);  // [KC][RP], zero-padded
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(NT) void assign_mfma_kernel(const float *__restrict
         if constexpr (kStageRows) {
             // four 16-byte loads in flight per lane, from clamped in-range
             // addresses and always issued, then their LDS stores; zero past r
-            // and past n (the odd pad column RP - 1 is never read)
+            // and past n (the pad columns RP - 2 and RP - 1 are never read)
             const int64_t left = n - g * 16;  // rows of this group that exist (>= 1)
             const v4f *fg = reinterpret_cast<const v4f *>(F + g * 16 * ldf);
             const int64_t ldq = ldf >> 2;
@@ -1067,7 +1073,7 @@ template <int NTILE>
 void assign_mfma(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C, int k, int32_t *labels,
                  float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
     constexpr int KC = 16 * NTILE;
-    const int64_t rp = ((r + 3) & ~int64_t(3)) + 1;
+    const int64_t rp = ((r + 3) & ~int64_t(3)) + 2;
     // rows staged in LDS (16-byte loads) up to 32 centroids, measured faster
     // there (1e6 x 96, k = 20: 0.24 -> 0.20 ms); with more centroids each lane
     // reads its row from F, with the loads of the next column steps in flight
@@ -1100,7 +1106,7 @@ void km_assign(const float *F, int64_t n, int64_t r, int64_t ldf, const float *C
                float *dist2, double *dist64, const KmBatch &b, hipStream_t s) {
     // matrix cores while the centroids fit 64 KB of LDS (the rows are staged
     // as well when they fit beside them)
-    const int64_t rpad = ((r + 3) & ~int64_t(3)) + 1;
+    const int64_t rpad = ((r + 3) & ~int64_t(3)) + 2;
     const int kc = ((k + 15) / 16) * 16;
     if (k >= 2 && k <= 64 && (size_t)kc * 16 + (size_t)kc * rpad * 4 <= 64 * 1024) {
         switch ((k + 15) / 16) {
