@@ -201,6 +201,27 @@ def test_kmeanspp_rejects_before_launch():
     assert L.asc_kmeanspp(fake, 100, 8, 8, 5, fake, fake, fake, ws - 1, None) == _abi.ASC_ERR_WORKSPACE
 
 
+def test_kmeans_replicates_rejects_before_launch():
+    L = _abi.lib()
+    fake = ctypes.c_void_p(0x1000)
+    n, r, k, reps = 100, 8, 5, 4
+    ws = L.asc_kmeans_replicates_workspace(n, r, k, reps)
+    # per run: centroids, labels, float64 distances, inertia and stamp, then the sums' partials
+    assert ws >= reps * (k * r * 4 + n * 4 + n * 8 + 8 + 4) + L.asc_kmeans_update_workspace(n, r, k)
+    assert L.asc_kmeans_replicates_workspace(n, r, k, 0) == 0
+    assert L.asc_kmeans_replicates_workspace(n, r, 0, reps) == 0
+
+    def call(F=fake, ldf=r, k_=k, reps_=reps, iters=10, rows=fake, labels=fake, C=fake, inertia=fake, wsb=ws):
+        return L.asc_kmeans_replicates(F, n, r, ldf, k_, reps_, iters, rows, labels, C, inertia, fake, wsb, None)
+
+    for kw in [dict(F=None), dict(ldf=r - 1), dict(k_=0), dict(k_=1025), dict(reps_=0), dict(reps_=65536),
+               dict(iters=-1), dict(iters=10001), dict(rows=None), dict(labels=None),
+               dict(labels=ctypes.c_void_p(0x1002)), dict(C=ctypes.c_void_p(0x1002)),
+               dict(inertia=ctypes.c_void_p(0x1004))]:
+        assert call(**kw) == _abi.ASC_ERR_INVALID, kw
+    assert call(wsb=ws - 1) == _abi.ASC_ERR_WORKSPACE
+
+
 def test_tuning_table_round_trip_and_file_format(tmp_path):
     L = _abi.lib()
     n, nnz, r = 123457, 999, 40
