@@ -112,6 +112,23 @@ def test_replicates_keep_least_inertia():
     assert rep0 == 0  # ties keep the lowest replicate
 
 
+def test_inertia_worked_example_and_lloyd_never_raises_it():
+    # by hand: rows (0,0) and (2,0) around (1,0) add 1 + 1, row (5,5) sits on
+    # its centroid and (5,7) is 2 above it: 1 + 1 + 0 + 4 = 6
+    F = np.array([[0, 0], [2, 0], [5, 5], [5, 7]], float)
+    assert oracle.inertia(F, np.array([[1, 0], [5, 5]], float), [0, 0, 1, 1]) == 6.0
+    # each Lloyd step (float64 centroids) lowers the inertia or keeps it
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((300, 3)) + np.repeat(rng.standard_normal((5, 3)) * 2, 60, axis=0)
+    C0 = F[rng.choice(300, 5, replace=False)]
+    prev = np.inf
+    for it in range(8):
+        labels, C = oracle.kmeans_lloyd(F, C0, it, np.float64)
+        e = oracle.inertia(F, C, labels)
+        assert e <= prev * (1 + 1e-12), (it, e, prev)
+        prev = e
+
+
 def test_gamma_peaks_at_the_number_of_cliques():
     # the detection property of Sec. 4.3: disjoint cliques (one bridge between
     # consecutive ones) are found identically by every realisation at k = 5
