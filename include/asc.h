@@ -257,8 +257,12 @@ asc_status asc_kmeans_update(const float *F, int64_t n, int64_t r, int64_t ldf, 
  * replicates): reps independent runs of Lloyd's method over the same F, run q
  * starting from C = F[rows[q*k + c]] (rows[reps*k], int32 on the device; an
  * out-of-range row reads row 0), each taking iters steps of
- * asc_kmeans_assign then asc_kmeans_update (same arithmetic, same results)
- * and a last assignment.  A run's inertia is sum_i min_c d(i, c), the
+ * asc_kmeans_assign then asc_kmeans_update and a last assignment.  The
+ * arithmetic is theirs; the centroid sums are split over as many partial
+ * blocks as in asc_kmeans_update (so the results are equal bit for bit)
+ * unless reps * ceil(n / 256) exceeds 16384, where fewer blocks per run take
+ * the rows (the float64 sums may then round differently before the float32
+ * means).  A run's inertia is sum_i min_c d(i, c), the
  * float64 distances of that assignment summed in a fixed order; the run of
  * least inertia (the lowest q on ties) gives labels[n] (int32) and, when C is
  * not NULL, its centroids C[k*r] (float32).  inertia[reps] (float64, may be
