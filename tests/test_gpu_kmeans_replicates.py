@@ -50,6 +50,7 @@ CASES = [
     (1000, 40, 100, 3, 8),
     (700, 64, 200, 2, 6),
     (10000, 6, 3, 5, 20),
+    (6000, 8, 6, 3, 10),  # 24 partial blocks, cut to 16 on both paths
     (500, 4, 1, 3, 5),
     (800, 8, 6, 4, 0),
     (333, 3, 4, 1, 10),
